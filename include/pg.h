@@ -1,0 +1,223 @@
+/*
+ * pg.h -- C ABI of libpg, a pattern-aware subgraph matcher for AMD MI355X
+ * (gfx950), after Peregrine (Jamshidi, Mahadasa, Vora; EuroSys 2020).
+ *
+ * The library turns a pattern into an exploration plan on the host
+ * (Sec. 4.1, Fig. "Computing exploration plan": symmetry-breaking partial
+ * order, core = minimum connected vertex cover, matching orders) and runs
+ * that plan on the GPU over a degree-ordered CSR graph resident in HBM
+ * (Sec. 5.1-5.2), counting the vertices outside the core by set sizes.
+ *
+ * Conventions shared by every entry point:
+ *  - Every call returns pg_status: PG_OK (0), PG_STOPPED (1, early exit),
+ *    or a negative error.  On error, pg_last_error() returns a message for
+ *    the calling thread.  No C++ exception crosses this interface.
+ *  - Pointers are host pointers unless the comment says "device".
+ *  - The caller owns every input array; the library copies what it keeps
+ *    during the call.  Objects returned through an out-pointer are owned by
+ *    the library until the matching pg_free_* call.
+ *  - hip_stream is a hipStream_t (NULL = the null stream).  Calls that take
+ *    one enqueue their GPU work on it and return after it completed.
+ *  - Vertex ids in results are the caller's original ids.
+ *  - Counts are exact unsigned 64-bit integers; a count that does not fit
+ *    returns PG_EOVERFLOW.
+ */
+#ifndef PG_H
+#define PG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pg_status;
+#define PG_OK 0
+#define PG_STOPPED 1
+#define PG_EINVAL (-1)        /* bad argument, malformed or unsupported pattern shape */
+#define PG_ENOMEM (-2)        /* host or device allocation failed */
+#define PG_EDEVICE (-3)       /* HIP runtime error */
+#define PG_EOVERFLOW (-4)     /* a count exceeds 2^64 - 1 */
+#define PG_EUNSUPPORTED (-5)  /* valid request this build does not handle */
+
+typedef struct pg_graph pg_graph;
+typedef struct pg_plan pg_plan;
+
+/* ------------------------------------------------------------------ graph */
+
+typedef struct {
+    int32_t device;       /* HIP device ordinal; -1 = the current device */
+    int32_t reserved[7];  /* must be zero */
+} pg_options;
+
+typedef struct {
+    int32_t n;            /* vertices (ids 0..n-1, isolated ones kept) */
+    int32_t d_max;        /* largest degree */
+    int64_t m;            /* distinct undirected edges after ingest */
+    int64_t device_bytes; /* HBM held by the resident graph */
+    int32_t labelled;     /* 1 if vertex labels were given */
+    int32_t device;       /* HIP device holding the graph */
+    const int32_t *perm;  /* host, n entries: perm[rank] = original id; owned by the graph */
+} pg_graph_info_t;
+
+/* Ingest an undirected graph and make it resident on the GPU (Sec. 5.1,
+ * 5.2): self-loops are dropped, duplicate and reversed pairs collapse into
+ * one edge, vertices are renumbered by ascending (degree, original id) --
+ * the degree order of Sec. 5.2 with ties broken by id -- and every
+ * adjacency list is sorted.
+ *   n       number of vertices, >= 1
+ *   m       number of input pairs, >= 0
+ *   src,dst m entries each, ids in [0, n)        (PG_EINVAL otherwise)
+ *   labels  n entries or NULL (unlabelled graph); values >= 0
+ *   opt     NULL for defaults
+ *   out     receives the graph; release with pg_free_graph */
+pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
+                        const int16_t *labels, const pg_options *opt, pg_graph **out);
+
+pg_status pg_graph_info(const pg_graph *g, pg_graph_info_t *out);
+
+/* Copy the resident CSR back to the host in rank ids: row_ptr n+1 entries,
+ * col 2m entries (each row ascending).  Either pointer may be NULL. */
+pg_status pg_graph_csr(const pg_graph *g, int64_t *row_ptr, int32_t *col);
+
+void pg_free_graph(pg_graph *g);
+
+/* ---------------------------------------------------------------- patterns */
+
+#define PG_EDGE 0       /* true edge: the two images must be adjacent (Sec. 2.1) */
+#define PG_ANTI_EDGE 1  /* anti-edge: the two images must not be adjacent (Sec. 3.1.1) */
+
+typedef struct {
+    int32_t u, v, type;  /* pattern vertex ids; type PG_EDGE or PG_ANTI_EDGE */
+} pg_edge;
+
+/* A pattern (Sec. 3.1, Fig. "Pattern Interface").
+ *   Regular vertices are 0..k-1 (2 <= k <= 16) and must be connected by
+ *   true edges.  Anti-vertices are k..k+n_anti_vertices-1 (at most 4); an
+ *   anti-vertex has only anti-edges, to regular vertices, at least one
+ *   (Sec. 3.1.2).  labels: k + n_anti_vertices entries or NULL; -1 = any.
+ *   induced = 1 adds an anti-edge between every pair of non-adjacent
+ *   regular vertices, which makes the count vertex-induced (the Theorem of
+ *   Sec. 3.1.3). */
+typedef struct {
+    int32_t k;
+    int32_t n_anti_vertices;
+    int32_t n_edges;
+    int32_t induced;
+    const pg_edge *edges;
+    const int16_t *labels;
+} pg_pattern_desc;
+
+/* ------------------------------------------------------------------- plans */
+
+#define PG_PLAN_AUTO 0          /* matching orders = linear extensions when few, else partial order only */
+#define PG_PLAN_LINEAR_EXT 1    /* always enumerate linear extensions of the core order (Sec. 4.1) */
+#define PG_PLAN_PARTIAL_ORDER 2 /* one program constrained only by the partial order */
+
+typedef struct {
+    int32_t mode;          /* PG_PLAN_* */
+    int32_t reserved[7];   /* must be zero */
+} pg_plan_options;
+
+typedef struct {
+    uint64_t aut;             /* |Aut_t|: permutations of the regular vertices preserving
+                                 edges, anti-edges, labels and anti-vertex neighbourhoods */
+    int32_t k;
+    int32_t core_size;
+    uint32_t core_mask;       /* bit u set: regular vertex u is in the core */
+    int32_t n_matching_orders;/* distinct matching orders (Sec. 4.1) */
+    int32_t n_programs;       /* count-mode programs after merging identical ones */
+    int32_t n_levels;         /* deepest program (levels evaluated on the GPU) */
+    int32_t n_order;          /* pairs in order[] */
+    int32_t order[240];       /* pairs (a, b): m(a) < m(b) is required (Grochow-Kellis) */
+    int32_t n_orbit_steps;    /* orbit_size[i]: orbit of the vertex fixed at step i */
+    int32_t orbit_size[16];   /* |Aut_t| = product of orbit_size[0..n_orbit_steps) */
+    int32_t orbit_vertex[16];
+    int32_t mode_used;        /* PG_PLAN_LINEAR_EXT or PG_PLAN_PARTIAL_ORDER */
+    double plan_ms;           /* host time to build the plan */
+} pg_plan_info_t;
+
+/* Build the exploration plan of a pattern (Sec. 4.1 Fig. "Computing
+ * exploration plan", Sec. 4.2-4.3).  Pure host computation.
+ * PG_EINVAL: k out of range, disconnected regular vertices, an edge that
+ * is both true and anti, an anti-vertex with a true edge or no anti-edge,
+ * ids out of range. */
+pg_status pg_plan_pattern(const pg_pattern_desc *p, pg_plan **out);
+pg_status pg_plan_pattern_ex(const pg_pattern_desc *p, const pg_plan_options *opt, pg_plan **out);
+pg_status pg_plan_info(const pg_plan *plan, pg_plan_info_t *out);
+void pg_free_plan(pg_plan *plan);
+
+/* Serialise the level programs the GPU interprets, for inspection and
+ * host-side checking.  enum_mode = 0: the count programs (merged, with
+ * multiplicities); 1: the enumeration programs.  buf: host, cap int32
+ * entries; *len receives the number of entries needed (PG_EINVAL with
+ * *len set when cap is too small).  Layout: n_programs, then per program
+ *   n_levels, mult_lo, mult_hi, and per level
+ *   isect diff lo hi excl t_isect t_diff base label group pv n_av,
+ *   then per anti-vertex check: nbr label xmask[16].
+ * Level masks are over earlier levels (bit y = level y); pv is the pattern
+ * vertex matched at the level; the last level counts C(|S|, group). */
+pg_status pg_plan_programs(const pg_plan *plan, int32_t enum_mode, int32_t *buf, int64_t cap, int64_t *len);
+
+/* ---------------------------------------------------------------- counting */
+
+typedef struct {
+    int32_t grid_waves;    /* persistent wavefronts; 0 = auto (CUs x waves per CU) */
+    int32_t chunk;         /* root tasks claimed per atomic; 0 = auto */
+    int32_t flags;         /* PG_RUN_* */
+    int32_t reserved[5];   /* must be zero */
+} pg_run_config;
+
+#define PG_RUN_COUNT_BYTES 1  /* also count the merge-model bytes of every set operation */
+#define PG_RUN_NO_MODE_B 2    /* never count by complement (|A| - |A & B|) */
+#define PG_RUN_ROOT_VERTEX 4  /* reserved */
+
+typedef struct {
+    double kernel_ms;        /* device time of the matching kernel (HIP events) */
+    double total_ms;         /* host wall time of the call */
+    uint64_t logical_bytes;  /* sum over set operations of 4 (|A| + |B|), if requested */
+    uint64_t root_tasks;     /* root tasks processed */
+    int32_t grid_waves;
+    int32_t chunk;
+} pg_run_stats;
+
+/* Count the matches of each plan (Sec. 3.2: count() is match() with a
+ * counting callback).  All plans run in one launch over one shared root
+ * frontier.  counts: host, n_plans entries, receives exact counts in the
+ * order of plans[].  Synchronous on hip_stream. */
+pg_status pg_count(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts,
+                   void *hip_stream);
+
+/* pg_count with launch knobs (NULL = defaults) and run statistics
+ * (NULL = not wanted).  Results do not depend on the knobs. */
+pg_status pg_count_ex(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts,
+                      const pg_run_config *cfg, pg_run_stats *stats, void *hip_stream);
+
+/* Existence query with early termination (Sec. 3.2.2, Sec. 5.3): found = 1
+ * if the pattern has at least one match.  Returns PG_OK either way. */
+pg_status pg_exists(pg_graph *g, const pg_plan *plan, int32_t *found, void *hip_stream);
+
+/* Enumerate every match once (one canonical representative per set of
+ * automorphic matches).  out: device memory of cap * k int32, row i holds
+ * match i as original vertex ids indexed by pattern vertex.  n_total
+ * receives the number of matches even when it exceeds cap (then only the
+ * first cap rows, in unspecified order, are written). */
+pg_status pg_enumerate(pg_graph *g, const pg_plan *plan, int32_t *out, uint64_t cap,
+                       uint64_t *n_total, void *hip_stream);
+
+/* Callback form of matching (Fig. "program examples", match(G, p, f)):
+ * ids holds k original vertex ids indexed by pattern vertex.  A nonzero
+ * return stops the exploration and the call returns PG_STOPPED.
+ * n_matches receives the number of callbacks made.  Runs on the null
+ * stream; the callback runs on the calling host thread. */
+typedef int (*pg_match_cb)(const int32_t *ids, int32_t k, void *user);
+pg_status pg_match(pg_graph *g, const pg_plan *plan, pg_match_cb cb, void *user, uint64_t *n_matches);
+
+/* Thread-local message for the last error on this thread ("" if none). */
+const char *pg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PG_H */

@@ -1,0 +1,610 @@
+// C ABI of libpg: graph store (ingest to a degree-ordered CSR resident in
+// HBM), plan handles, and the count / exists / enumerate / match calls that
+// launch the matching kernel.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+#include "pg_internal.hpp"
+
+namespace pg {
+
+namespace {
+thread_local std::string g_err;
+}
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+}  // namespace pg
+
+using pg::set_error;
+
+#define PG_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));             \
+            return PG_EDEVICE;                                                        \
+        }                                                                             \
+    } while (0)
+
+namespace {
+inline void dfree(void *p) {
+    if (p) (void)hipFree(p);
+}
+inline void edestroy(hipEvent_t e) { (void)hipEventDestroy(e); }
+}  // namespace
+
+struct pg_graph {
+    int32_t n = 0;
+    int64_t m = 0;
+    int32_t d_max = 0;
+    int32_t device = 0;
+    int32_t n_cu = 0;
+    bool labelled = false;
+    std::vector<int32_t> perm;  // rank -> original id
+    // device arrays
+    int64_t *rp = nullptr;
+    int32_t *col = nullptr;
+    int16_t *lab = nullptr;
+    int32_t *dperm = nullptr;
+    int32_t *tsrc = nullptr;
+    int32_t *tdst = nullptr;
+    int64_t device_bytes = 0;
+    // per-call buffers, grown on demand
+    std::mutex mu;
+    int32_t *scratch = nullptr;
+    size_t scratch_ints = 0;
+    void *trie_buf = nullptr;
+    size_t trie_bytes = 0;
+    unsigned long long *ctl = nullptr;  // counts[64], cursor, emit_ctr, bytes, flags[2]
+    // cached trie of the last launch
+    std::vector<const pg_plan *> trie_key;
+    bool trie_emit = false;
+    pg::Trie trie;
+    bool trie_valid = false;
+
+    ~pg_graph() {
+        dfree(rp);
+        dfree(col);
+        dfree(lab);
+        dfree(dperm);
+        dfree(tsrc);
+        dfree(tdst);
+        dfree(scratch);
+        dfree(trie_buf);
+        dfree(ctl);
+    }
+};
+
+namespace {
+
+constexpr int kCtlCounts = 0;
+constexpr int kCtlCursor = 64;
+constexpr int kCtlEmit = 65;
+constexpr int kCtlBytes = 66;
+constexpr int kCtlFlags = 67;  // two int32 in one slot
+constexpr int kCtlWords = 68;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+template <class T>
+pg_status upload(T **dst, const std::vector<T> &src, int64_t *bytes) {
+    size_t nb = std::max<size_t>(1, src.size()) * sizeof(T);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), nb);
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc: ") + hipGetErrorString(e));
+        return PG_ENOMEM;
+    }
+    if (!src.empty()) PG_HIP(hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+    *bytes += (int64_t)nb;
+    return PG_OK;
+}
+
+// LSD radix sort of 64-bit keys, 16 bits per pass.
+void radix_sort_u64(std::vector<uint64_t> &a, int key_bits) {
+    std::vector<uint64_t> tmp(a.size());
+    std::vector<size_t> cnt(1 << 16);
+    for (int shift = 0; shift < key_bits; shift += 16) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (uint64_t x : a) cnt[(x >> shift) & 0xFFFF]++;
+        size_t s = 0;
+        for (auto &c : cnt) {
+            size_t t = c;
+            c = s;
+            s += t;
+        }
+        for (uint64_t x : a) tmp[cnt[(x >> shift) & 0xFFFF]++] = x;
+        a.swap(tmp);
+    }
+}
+
+int bits_for(uint64_t v) {
+    int b = 0;
+    while (b < 64 && (v >> b)) b++;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pg_last_error(void) { return pg::g_err.c_str(); }
+
+pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int16_t *labels,
+                        const pg_options *opt, pg_graph **out) {
+    try {
+        if (!out) { set_error("out is NULL"); return PG_EINVAL; }
+        *out = nullptr;
+        if (n < 1) { set_error("n must be >= 1"); return PG_EINVAL; }
+        if (m < 0 || (m > 0 && (!src || !dst))) { set_error("bad edge arrays"); return PG_EINVAL; }
+        if (opt) {
+            for (int i = 0; i < 7; i++)
+                if (opt->reserved[i]) { set_error("pg_options.reserved must be zero"); return PG_EINVAL; }
+        }
+        int dev = opt ? opt->device : -1;
+        if (dev < 0) PG_HIP(hipGetDevice(&dev));
+        int ndev = 0;
+        PG_HIP(hipGetDeviceCount(&ndev));
+        if (dev >= ndev) { set_error("device out of range"); return PG_EINVAL; }
+        DeviceGuard guard(dev);
+
+        // 1. canonical undirected simple edge set (Sec. 2.1)
+        std::vector<uint64_t> keys;
+        keys.reserve((size_t)m);
+        for (int64_t i = 0; i < m; i++) {
+            int32_t a = src[i], b = dst[i];
+            if (a < 0 || b < 0 || a >= n || b >= n) {
+                set_error("edge endpoint out of range at index " + std::to_string(i));
+                return PG_EINVAL;
+            }
+            if (a == b) continue;
+            if (a > b) std::swap(a, b);
+            keys.push_back((uint64_t)(uint32_t)a << 32 | (uint32_t)b);
+        }
+        radix_sort_u64(keys, 32 + bits_for((uint64_t)n));
+        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
+        const int64_t mu = (int64_t)keys.size();
+        if (2 * mu > (int64_t)INT32_MAX * 64) { set_error("graph too large"); return PG_EUNSUPPORTED; }
+
+        // 2. degree order: rank by (degree, original id) ascending (Sec. 5.2)
+        std::vector<int64_t> deg(n, 0);
+        for (uint64_t k : keys) {
+            deg[k >> 32]++;
+            deg[k & 0xFFFFFFFFu]++;
+        }
+        int64_t dmax = 0;
+        for (int64_t d : deg) dmax = std::max(dmax, d);
+        if (dmax > INT32_MAX / 2) { set_error("degree too large"); return PG_EUNSUPPORTED; }
+        std::vector<int64_t> dstart(dmax + 2, 0);
+        for (int64_t d : deg) dstart[d + 1]++;
+        for (int64_t d = 0; d <= dmax; d++) dstart[d + 1] += dstart[d];
+        std::vector<int32_t> rank(n), perm(n);
+        for (int32_t v = 0; v < n; v++) {
+            int32_t r = (int32_t)dstart[deg[v]]++;
+            rank[v] = r;
+            perm[r] = v;
+        }
+
+        // 3. CSR in rank ids, rows sorted ascending
+        std::vector<int64_t> rp(n + 1, 0);
+        for (int32_t r = 0; r < n; r++) rp[r + 1] = rp[r] + deg[perm[r]];
+        std::vector<int32_t> col((size_t)(2 * mu));
+        {
+            std::vector<int64_t> fill(rp.begin(), rp.end() - 1);
+            for (uint64_t k : keys) {
+                int32_t a = rank[k >> 32], b = rank[k & 0xFFFFFFFFu];
+                col[fill[a]++] = b;
+                col[fill[b]++] = a;
+            }
+        }
+        keys.clear();
+        keys.shrink_to_fit();
+        for (int32_t r = 0; r < n; r++) std::sort(col.begin() + rp[r], col.begin() + rp[r + 1]);
+
+        // 4. root edge tasks u < v, costliest first (Sec. 5.2: start with the
+        //    highest-degree vertices); cost estimate d(u) + d(v)
+        std::vector<int32_t> tsrc((size_t)mu), tdst((size_t)mu);
+        {
+            std::vector<int64_t> cstart(2 * dmax + 3, 0);
+            for (int32_t u = 0; u < n; u++)
+                for (int64_t e = rp[u]; e < rp[u + 1]; e++)
+                    if (col[e] > u) cstart[2 * dmax - (deg[perm[u]] + deg[perm[col[e]]]) + 1]++;
+            for (size_t i = 1; i < cstart.size(); i++) cstart[i] += cstart[i - 1];
+            for (int32_t u = 0; u < n; u++)
+                for (int64_t e = rp[u]; e < rp[u + 1]; e++)
+                    if (col[e] > u) {
+                        int64_t slot = cstart[2 * dmax - (deg[perm[u]] + deg[perm[col[e]]])]++;
+                        tsrc[slot] = u;
+                        tdst[slot] = col[e];
+                    }
+        }
+        std::vector<int16_t> lab;
+        if (labels) {
+            lab.resize(n);
+            for (int32_t v = 0; v < n; v++) {
+                if (labels[v] < 0) { set_error("labels must be >= 0"); return PG_EINVAL; }
+                lab[rank[v]] = labels[v];
+            }
+        }
+
+        std::unique_ptr<pg_graph> g(new pg_graph());
+        g->n = n;
+        g->m = mu;
+        g->d_max = (int32_t)dmax;
+        g->device = dev;
+        g->labelled = labels != nullptr;
+        hipDeviceProp_t prop;
+        PG_HIP(hipGetDeviceProperties(&prop, dev));
+        g->n_cu = prop.multiProcessorCount;
+        pg_status st;
+        if ((st = upload(&g->rp, rp, &g->device_bytes))) return st;
+        if ((st = upload(&g->col, col, &g->device_bytes))) return st;
+        if ((st = upload(&g->dperm, perm, &g->device_bytes))) return st;
+        if ((st = upload(&g->tsrc, tsrc, &g->device_bytes))) return st;
+        if ((st = upload(&g->tdst, tdst, &g->device_bytes))) return st;
+        if (labels && (st = upload(&g->lab, lab, &g->device_bytes))) return st;
+        PG_HIP(hipMalloc(reinterpret_cast<void **>(&g->ctl), kCtlWords * sizeof(unsigned long long)));
+        g->perm = std::move(perm);
+        *out = g.release();
+        return PG_OK;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return PG_EINVAL;
+    }
+}
+
+pg_status pg_graph_info(const pg_graph *g, pg_graph_info_t *out) {
+    if (!g || !out) { set_error("NULL argument"); return PG_EINVAL; }
+    std::memset(out, 0, sizeof(*out));
+    out->n = g->n;
+    out->m = g->m;
+    out->d_max = g->d_max;
+    out->device_bytes = g->device_bytes;
+    out->labelled = g->labelled ? 1 : 0;
+    out->device = g->device;
+    out->perm = g->perm.data();
+    return PG_OK;
+}
+
+pg_status pg_graph_csr(const pg_graph *g, int64_t *row_ptr, int32_t *col) {
+    if (!g) { set_error("NULL graph"); return PG_EINVAL; }
+    DeviceGuard guard(g->device);
+    if (row_ptr) PG_HIP(hipMemcpy(row_ptr, g->rp, sizeof(int64_t) * (size_t)(g->n + 1), hipMemcpyDeviceToHost));
+    if (col && g->m) PG_HIP(hipMemcpy(col, g->col, sizeof(int32_t) * (size_t)(2 * g->m), hipMemcpyDeviceToHost));
+    return PG_OK;
+}
+
+void pg_free_graph(pg_graph *g) {
+    if (!g) return;
+    DeviceGuard guard(g->device);
+    delete g;
+}
+
+pg_status pg_plan_pattern_ex(const pg_pattern_desc *p, const pg_plan_options *opt, pg_plan **out) {
+    try {
+        if (!out) { set_error("out is NULL"); return PG_EINVAL; }
+        *out = nullptr;
+        if (opt)
+            for (int i = 0; i < 7; i++)
+                if (opt->reserved[i]) { set_error("pg_plan_options.reserved must be zero"); return PG_EINVAL; }
+        std::unique_ptr<pg_plan> plan(new pg_plan());
+        std::string err;
+        pg_status st = pg::compile_plan(p, opt, &plan->impl, &err);
+        if (st) {
+            set_error(err);
+            return st;
+        }
+        *out = plan.release();
+        return PG_OK;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    }
+}
+
+pg_status pg_plan_pattern(const pg_pattern_desc *p, pg_plan **out) { return pg_plan_pattern_ex(p, nullptr, out); }
+
+pg_status pg_plan_info(const pg_plan *plan, pg_plan_info_t *out) {
+    if (!plan || !out) { set_error("NULL argument"); return PG_EINVAL; }
+    *out = plan->impl.info;
+    return PG_OK;
+}
+
+void pg_free_plan(pg_plan *plan) { delete plan; }
+
+pg_status pg_plan_programs(const pg_plan *plan, int32_t enum_mode, int32_t *buf, int64_t cap, int64_t *len) {
+    if (!plan || !len) { set_error("NULL argument"); return PG_EINVAL; }
+    const auto &progs = enum_mode ? plan->impl.enum_progs : plan->impl.count_progs;
+    std::vector<int32_t> v;
+    v.push_back((int32_t)progs.size());
+    for (const pg::Program &p : progs) {
+        v.push_back((int32_t)p.lev.size());
+        v.push_back((int32_t)(uint32_t)(p.mult & 0xFFFFFFFFu));
+        v.push_back((int32_t)(uint32_t)(p.mult >> 32));
+        for (const pg::Level &L : p.lev) {
+            for (uint32_t x : {L.isect, L.diff, L.lo, L.hi, L.excl, L.t_isect, L.t_diff}) v.push_back((int32_t)x);
+            v.push_back(L.base);
+            v.push_back(L.label);
+            v.push_back(L.group);
+            v.push_back(L.pv);
+            v.push_back((int32_t)L.avs.size());
+            for (const pg::AVCheck &c : L.avs) {
+                v.push_back((int32_t)c.nbr);
+                v.push_back(c.label);
+                for (int i = 0; i < pg::kMaxLevels; i++) v.push_back((int32_t)c.xmask[i]);
+            }
+        }
+    }
+    *len = (int64_t)v.size();
+    if (!buf || cap < (int64_t)v.size()) { set_error("buffer too small"); return PG_EINVAL; }
+    std::memcpy(buf, v.data(), v.size() * sizeof(int32_t));
+    return PG_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct LaunchArgs {
+    int mode = pg::kModeCount;
+    int32_t *out = nullptr;
+    uint64_t cap = 0;
+};
+
+pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts, const pg_run_config *cfg,
+              pg_run_stats *stats, void *hip_stream, const LaunchArgs &la, uint64_t *emitted) {
+    auto t_start = std::chrono::steady_clock::now();
+    if (!g) { set_error("NULL graph"); return PG_EINVAL; }
+    if (n_plans < 1 || n_plans > pg::kMaxPlansPerLaunch) { set_error("n_plans must be in [1, 64]"); return PG_EINVAL; }
+    if (!plans) { set_error("plans is NULL"); return PG_EINVAL; }
+    for (int i = 0; i < n_plans; i++)
+        if (!plans[i]) { set_error("a plan is NULL"); return PG_EINVAL; }
+    if (cfg) {
+        if (cfg->grid_waves < 0 || cfg->chunk < 0) { set_error("negative launch knob"); return PG_EINVAL; }
+        for (int i = 0; i < 5; i++)
+            if (cfg->reserved[i]) { set_error("pg_run_config.reserved must be zero"); return PG_EINVAL; }
+    }
+    std::lock_guard<std::mutex> lock(g->mu);
+    DeviceGuard guard(g->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const bool emit = la.mode == pg::kModeEmit;
+
+    // program trie (cached for a repeated plan list)
+    std::vector<const pg_plan *> key(plans, plans + n_plans);
+    if (!g->trie_valid || g->trie_key != key || g->trie_emit != emit) {
+        std::vector<const pg::PlanImpl *> impls;
+        for (int i = 0; i < n_plans; i++) impls.push_back(&plans[i]->impl);
+        g->trie = pg::build_trie(impls, emit);
+        g->trie_key = key;
+        g->trie_emit = emit;
+        g->trie_valid = true;
+    }
+    const pg::Trie &T = g->trie;
+    if (T.max_level > pg::kMaxLevels) { set_error("plan too deep"); return PG_EUNSUPPORTED; }
+
+    // upload the trie: nodes | avs | roots
+    size_t nb = T.nodes.size() * sizeof(pg::Node), ab = T.avs.size() * sizeof(pg::AVCheck),
+           rb = T.roots.size() * sizeof(int32_t);
+    size_t need = nb + ab + rb + 64;
+    if (need > g->trie_bytes) {
+        dfree(g->trie_buf);
+        g->trie_buf = nullptr;
+        g->trie_bytes = 0;
+        if (hipMalloc(&g->trie_buf, need) != hipSuccess) { set_error("hipMalloc trie"); return PG_ENOMEM; }
+        g->trie_bytes = need;
+    }
+    std::vector<char> host(need, 0);
+    std::memcpy(host.data(), T.nodes.data(), nb);
+    size_t a_off = (nb + 15) & ~size_t(15);
+    std::memcpy(host.data() + a_off, T.avs.data(), ab);
+    size_t r_off = (a_off + ab + 15) & ~size_t(15);
+    std::memcpy(host.data() + r_off, T.roots.data(), rb);
+    PG_HIP(hipMemcpyAsync(g->trie_buf, host.data(), need, hipMemcpyHostToDevice, s));
+
+    // launch shape
+    int grid = cfg && cfg->grid_waves ? cfg->grid_waves : g->n_cu * 8;
+    const long long n_et = T.has_edge_root ? (long long)g->m : 0;
+    const long long n_vt = T.has_vertex_root ? (long long)g->n : 0;
+    int chunk = cfg && cfg->chunk ? cfg->chunk : 64;
+    // scratch: one set per enumeration level (levels 2 .. max_level-2)
+    const int enum_levels = std::max(0, T.max_level - 3);
+    const long long set_cap = std::max<long long>(1, g->d_max);
+    const size_t need_ints = (size_t)grid * (size_t)enum_levels * (size_t)set_cap;
+    if (need_ints > g->scratch_ints) {
+        dfree(g->scratch);
+        g->scratch = nullptr;
+        g->scratch_ints = 0;
+        if (hipMalloc(reinterpret_cast<void **>(&g->scratch), need_ints * sizeof(int32_t)) != hipSuccess) {
+            set_error("hipMalloc scratch");
+            return PG_ENOMEM;
+        }
+        g->scratch_ints = need_ints;
+    }
+    PG_HIP(hipMemsetAsync(g->ctl, 0, kCtlWords * sizeof(unsigned long long), s));
+
+    pg::KParams P;
+    std::memset(&P, 0, sizeof(P));
+    P.rp = g->rp;
+    P.col = g->col;
+    P.lab = g->lab;
+    P.perm = g->dperm;
+    P.tsrc = g->tsrc;
+    P.tdst = g->tdst;
+    P.nodes = reinterpret_cast<const pg::Node *>(g->trie_buf);
+    P.avs = reinterpret_cast<const pg::AVCheck *>(static_cast<char *>(g->trie_buf) + a_off);
+    P.roots = reinterpret_cast<const int32_t *>(static_cast<char *>(g->trie_buf) + r_off);
+    P.cursor = g->ctl + kCtlCursor;
+    P.counts = g->ctl + kCtlCounts;
+    P.flags = reinterpret_cast<int32_t *>(g->ctl + kCtlFlags);
+    P.emit_ctr = g->ctl + kCtlEmit;
+    P.out = la.out;
+    P.bytes_ctr = g->ctl + kCtlBytes;
+    P.scratch = enum_levels ? g->scratch : nullptr;
+    P.wave_stride = (long long)enum_levels * set_cap;
+    P.set_cap = set_cap;
+    P.n_etasks = n_et;
+    P.n_vtasks = n_vt;
+    P.cap = la.cap;
+    P.n = g->n;
+    P.n_roots = (int32_t)T.roots.size();
+    P.chunk = chunk;
+    P.n_plans = n_plans;
+    P.mode = la.mode;
+    P.run_flags = cfg ? cfg->flags : 0;
+
+    hipEvent_t e0, e1;
+    PG_HIP(hipEventCreate(&e0));
+    PG_HIP(hipEventCreate(&e1));
+    PG_HIP(hipEventRecord(e0, s));
+    hipError_t le = pg::launch_match(P, grid, s);
+    if (le != hipSuccess) {
+        edestroy(e0);
+        edestroy(e1);
+        set_error(std::string("kernel launch: ") + hipGetErrorString(le));
+        return PG_EDEVICE;
+    }
+    PG_HIP(hipEventRecord(e1, s));
+    unsigned long long ctl[kCtlWords];
+    PG_HIP(hipMemcpyAsync(ctl, g->ctl, sizeof(ctl), hipMemcpyDeviceToHost, s));
+    PG_HIP(hipStreamSynchronize(s));
+    float ms = 0.f;
+    PG_HIP(hipEventElapsedTime(&ms, e0, e1));
+    edestroy(e0);
+    edestroy(e1);
+    const int32_t *flags = reinterpret_cast<const int32_t *>(ctl + kCtlFlags);
+    if (counts)
+        for (int i = 0; i < n_plans; i++) counts[i] = ctl[kCtlCounts + i];
+    if (emitted) *emitted = ctl[kCtlEmit];
+    if (stats) {
+        stats->kernel_ms = ms;
+        stats->total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+        stats->logical_bytes = ctl[kCtlBytes];
+        stats->root_tasks = (uint64_t)(n_et + n_vt);
+        stats->grid_waves = grid;
+        stats->chunk = chunk;
+    }
+    if (flags[0]) {
+        set_error("a count exceeds 2^64 - 1");
+        return PG_EOVERFLOW;
+    }
+    return PG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pg_status pg_count_ex(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts,
+                      const pg_run_config *cfg, pg_run_stats *stats, void *hip_stream) {
+    if (!counts) { set_error("counts is NULL"); return PG_EINVAL; }
+    try {
+        return run(g, plans, n_plans, counts, cfg, stats, hip_stream, LaunchArgs{}, nullptr);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    }
+}
+
+pg_status pg_count(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts, void *hip_stream) {
+    return pg_count_ex(g, plans, n_plans, counts, nullptr, nullptr, hip_stream);
+}
+
+pg_status pg_exists(pg_graph *g, const pg_plan *plan, int32_t *found, void *hip_stream) {
+    if (!found || !plan) { set_error("NULL argument"); return PG_EINVAL; }
+    LaunchArgs la;
+    la.mode = pg::kModeExists;
+    uint64_t c = 0;
+    const pg_plan *plans[1] = {plan};
+    pg_run_config cfg;
+    std::memset(&cfg, 0, sizeof(cfg));
+    cfg.chunk = 1;
+    try {
+        pg_status st = run(g, plans, 1, &c, &cfg, nullptr, hip_stream, la, nullptr);
+        if (st == PG_EOVERFLOW) st = PG_OK;  // partial sums may wrap once a match is found
+        if (st) return st;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    }
+    *found = c > 0 ? 1 : 0;
+    return PG_OK;
+}
+
+pg_status pg_enumerate(pg_graph *g, const pg_plan *plan, int32_t *out, uint64_t cap, uint64_t *n_total,
+                       void *hip_stream) {
+    if (!plan || !n_total) { set_error("NULL argument"); return PG_EINVAL; }
+    if (cap > 0 && !out) { set_error("out is NULL with cap > 0"); return PG_EINVAL; }
+    LaunchArgs la;
+    la.mode = pg::kModeEmit;
+    la.out = out;
+    la.cap = cap;
+    const pg_plan *plans[1] = {plan};
+    try {
+        return run(g, plans, 1, nullptr, nullptr, nullptr, hip_stream, la, n_total);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    }
+}
+
+pg_status pg_match(pg_graph *g, const pg_plan *plan, pg_match_cb cb, void *user, uint64_t *n_matches) {
+    if (!g || !plan || !cb) { set_error("NULL argument"); return PG_EINVAL; }
+    if (n_matches) *n_matches = 0;
+    uint64_t total = 0;
+    pg_status st = pg_enumerate(g, plan, nullptr, 0, &total, nullptr);
+    if (st) return st;
+    if (total == 0) return PG_OK;
+    const int k = plan->impl.k;
+    const uint64_t kMaxRows = (uint64_t)1 << 26;
+    if (total > kMaxRows) { set_error("too many matches for the callback form"); return PG_EUNSUPPORTED; }
+    DeviceGuard guard(g->device);
+    int32_t *d = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&d), total * (uint64_t)k * sizeof(int32_t)) != hipSuccess) {
+        set_error("hipMalloc match rows");
+        return PG_ENOMEM;
+    }
+    uint64_t got = 0;
+    st = pg_enumerate(g, plan, d, total, &got, nullptr);
+    std::vector<int32_t> h;
+    if (!st) {
+        h.resize(total * (uint64_t)k);
+        if (hipMemcpy(h.data(), d, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
+            set_error("copy of match rows failed");
+            st = PG_EDEVICE;
+        }
+    }
+    dfree(d);
+    if (st) return st;
+    for (uint64_t i = 0; i < total; i++) {
+        if (n_matches) (*n_matches)++;
+        if (cb(h.data() + i * (uint64_t)k, k, user)) return PG_STOPPED;
+    }
+    return PG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,44 @@
+// Launch interface of the matching kernel (host <-> device parameter block).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pg_internal.hpp"
+
+namespace pg {
+
+enum RunMode : int32_t { kModeCount = 0, kModeExists = 1, kModeEmit = 2 };
+
+struct KParams {
+    const int64_t *rp;
+    const int32_t *col;
+    const int16_t *lab;
+    const int32_t *perm;
+    const int32_t *tsrc;
+    const int32_t *tdst;
+    const Node *nodes;
+    const AVCheck *avs;
+    const int32_t *roots;
+    unsigned long long *cursor;
+    unsigned long long *counts;
+    int32_t *flags;            // [0] overflow, [1] stop
+    unsigned long long *emit_ctr;
+    int32_t *out;
+    unsigned long long *bytes_ctr;
+    int32_t *scratch;
+    long long wave_stride;     // ints per wave
+    long long set_cap;         // ints per materialised level
+    long long n_etasks;
+    long long n_vtasks;
+    unsigned long long cap;    // emit capacity (rows)
+    int32_t n;
+    int32_t n_roots;
+    int32_t chunk;
+    int32_t n_plans;
+    int32_t mode;
+    int32_t run_flags;
+};
+
+hipError_t launch_match(const KParams &P, int grid, hipStream_t s);
+
+}  // namespace pg

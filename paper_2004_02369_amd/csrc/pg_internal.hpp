@@ -1,0 +1,110 @@
+// Internal types of libpg shared by the host plan compiler, the graph
+// store and the HIP engine.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/pg.h"
+
+namespace pg {
+
+constexpr int kMaxK = 16;       // regular pattern vertices
+constexpr int kMaxAV = 4;       // anti-vertices
+constexpr int kMaxLevels = 16;  // GPU levels per program (one per matched pattern vertex)
+constexpr int kMaxPlansPerLaunch = 64;
+
+// Kinds of program-trie nodes.  A "level" is one pattern vertex matched on
+// the GPU; level 0 and 1 of edge-rooted programs come from a root task.
+enum NodeKind : int32_t {
+    kRootVertex = 0,  // root task = one vertex (level 0); children are count nodes at level 1
+    kRootEdge = 1,    // root task = one oriented edge u < v (levels 0, 1)
+    kEnum = 2,        // materialise this level's candidate set, then descend per candidate
+    kCount = 3,       // add C(|candidates|, group) * mult to counts[plan]
+    kEmit = 4,        // write one match row per candidate
+};
+
+// Anti-vertex constraint (Sec. 3.1.2 / Sec. 4.3), evaluated for a candidate
+// once every vertex it depends on is matched: no data vertex lies in all
+// sets N(m(a)) \ m(true pattern neighbours of a), a over its neighbours.
+struct AVCheck {
+    uint32_t nbr;                 // levels of the anti-vertex's regular neighbours
+    int32_t label;                // -1 = any
+    uint32_t xmask[kMaxLevels];   // per neighbour level a: levels of a's true pattern neighbours
+};
+
+// One node of the program trie, laid out for the device.  All masks are
+// over levels strictly below `level`.
+struct Node {
+    int32_t kind;
+    int32_t level;
+    uint32_t isect;    // candidates must be adjacent to these levels' images (true edges)
+    uint32_t diff;     // ... and not adjacent to these (anti-edges)
+    uint32_t lo;       // ... and larger than these images (partial / matching order)
+    uint32_t hi;       // ... and smaller than these
+    uint32_t excl;     // ... and different from these (injectivity not implied otherwise)
+    uint32_t t_isect;  // isect levels still to test once the base set is used
+    uint32_t t_diff;   // diff levels still to test once the base set is used
+    int32_t base;      // materialised ancestor level whose set contains every candidate; -1 none
+    int32_t label;     // -1 = any
+    int32_t group;     // count: number of interchangeable vertices counted as C(n, group)
+    int32_t av_begin;  // anti-vertex checks applied to this node's candidates
+    int32_t av_count;
+    int32_t plan;      // count / emit: output slot
+    int32_t child_begin;
+    int32_t child_count;
+    int32_t k;         // emit: pattern size
+    uint64_t mult;     // count: multiplicity (identical programs merged)
+    int32_t label0;    // root nodes: labels of level 0 and level 1
+    int32_t label1;
+    int8_t pv[kMaxLevels];  // emit: pattern vertex matched at each level
+};
+
+// A program: one matching order with its completion, as a sequence of levels.
+struct Level {
+    uint32_t isect = 0, diff = 0, lo = 0, hi = 0, excl = 0;
+    uint32_t t_isect = 0, t_diff = 0;
+    int32_t base = -1;
+    int32_t label = -1;
+    int32_t group = 1;
+    int32_t pv = -1;
+    std::vector<AVCheck> avs;  // checks applied to this level's candidates
+};
+
+struct Program {
+    std::vector<Level> lev;    // last level is the count / emit level
+    uint64_t mult = 1;
+};
+
+struct PlanImpl {
+    pg_plan_info_t info{};
+    int32_t k = 0;
+    std::vector<Program> count_progs;  // merged, with multiplicities
+    std::vector<Program> enum_progs;   // one per matching order, every vertex its own level
+};
+
+// The trie of all programs of one launch, flattened for upload.
+struct Trie {
+    std::vector<Node> nodes;
+    std::vector<AVCheck> avs;
+    std::vector<int32_t> roots;   // node ids of root nodes
+    int32_t max_level = 0;        // deepest level index + 1
+    bool has_vertex_root = false;
+    bool has_edge_root = false;
+};
+
+Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit);
+
+// Plan compiler entry (host only).
+pg_status compile_plan(const pg_pattern_desc *desc, const pg_plan_options *opt, PlanImpl *out,
+                       std::string *err);
+
+void set_error(const std::string &msg);
+
+}  // namespace pg
+
+struct pg_plan {
+    pg::PlanImpl impl;
+};

@@ -1,0 +1,241 @@
+"""Host-side tests of libpg (no GPU needed): the C ABI loads and exports
+every declared symbol, the plan compiler reproduces the paper's worked
+example and textbook symmetry counts, and the programs it emits -- run by
+a slow literal interpreter -- give the oracle's counts and match sets."""
+import itertools
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from paper_2004_02369_amd import graphgen as gg
+from paper_2004_02369_amd import patterns as pt
+from paper_2004_02369_amd import pg
+from tests.plan_interp import interp_count, interp_enumerate
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def built():
+    if not os.path.exists(pg.LIB_PATH):
+        from paper_2004_02369_amd import build
+        build.build()
+
+
+def header_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:const\s+)?[\w]+\s*\**\s*(pg_\w+)\s*\(", txt, flags=re.M))
+    return names
+
+
+def test_abi_exports_every_declared_symbol():
+    names = header_functions()
+    assert {"pg_load_graph", "pg_count", "pg_enumerate", "pg_match", "pg_exists", "pg_last_error"} <= names
+    L = pg.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+    assert set(pg.EXPORTS) == names
+
+
+# ------------------------------------------------------------ worked example
+
+DIAMOND = {"k": 4, "edges": [(0, 1), (1, 2), (2, 3), (3, 0), (1, 3)]}   # u1..u4 = 0..3, chord u2-u4
+
+
+def test_diamond_plan_matches_paper():
+    """Sec. 4.1: partial order u1 < u3, u2 < u4; core {u2, u4}; one matching order."""
+    info = pg.plan_pattern(DIAMOND).info()
+    assert sorted(info["order"]) == [(0, 2), (1, 3)]
+    assert info["core"] == [1, 3]
+    assert info["n_matching_orders"] == 1
+    assert info["aut"] == 4
+
+
+@pytest.mark.parametrize("spec,aut", [
+    (pt.clique(3), 6), (pt.clique(4), 24), (pt.clique(5), 120), (pt.clique(14), math.factorial(14)),
+    (pt.star(3), 2), (pt.star(4), 6), (pt.star(5), 24), (pt.chain(4), 2), (pt.chain(6), 2),
+    ({"k": 5, "edges": [(i, (i + 1) % 5) for i in range(5)]}, 10), (DIAMOND, 4),
+    ({"k": 4, "edges": [(0, 1), (1, 2), (2, 0), (0, 3)]}, 2),
+    (pt.P7_TRIANGLE_NO_K4, 6), (pt.P8_INDUCED_DIAMOND, 4), (pt.PA_TWO_COMMON_FRIENDS, 4),
+])
+def test_aut_and_orbit_product(spec, aut, orc):
+    info = pg.plan_pattern(spec).info()
+    assert info["aut"] == aut
+    assert math.prod(info["orbit_size"]) == aut
+    if spec["k"] <= 8:
+        assert orc.aut(spec) == aut
+
+
+def test_plan_time_small():
+    for spec in pt.all_vertex_induced(5) + [pt.clique(14)]:
+        assert pg.plan_pattern(spec).info()["plan_ms"] < 50.0
+
+
+def test_generator_cardinalities():
+    assert [len(pt.all_vertex_induced(k)) for k in (2, 3, 4, 5)] == [1, 2, 6, 21]
+    assert len(pt.all_edge_induced(3)) == 3
+    assert len(pt.all_edge_induced(2)) == 1
+
+
+def _min_connected_cover_size(spec):
+    k = spec["k"]
+    E = {tuple(sorted(e)) for e in spec["edges"]}
+    A = {tuple(sorted(e)) for e in spec.get("anti", []) or []}
+    if spec.get("induced"):
+        A |= {p for p in itertools.combinations(range(k), 2) if p not in E}
+    for s in range(1, k + 1):
+        for S in itertools.combinations(range(k), s):
+            S = set(S)
+            if any(a not in S and b not in S for a, b in E | A):
+                continue
+            seen, todo = {min(S)}, [min(S)]
+            while todo:
+                x = todo.pop()
+                for a, b in E:
+                    for u, w in ((a, b), (b, a)):
+                        if u == x and w in S and w not in seen:
+                            seen.add(w)
+                            todo.append(w)
+            if seen == S:
+                return s
+    return k
+
+
+PLAN_PATTERNS = (pt.all_vertex_induced(3) + pt.all_vertex_induced(4) + pt.all_vertex_induced(5)
+                 + [pt.clique(k) for k in (3, 4, 5, 6)] + [pt.star(k) for k in (2, 3, 4, 5)]
+                 + [pt.chain(k) for k in (3, 4, 5)] + pt.all_edge_induced(3) + pt.all_edge_induced(4)
+                 + [DIAMOND, pt.P7_TRIANGLE_NO_K4, pt.P8_INDUCED_DIAMOND, pt.PA_TWO_COMMON_FRIENDS,
+                    {"k": 4, "edges": [(0, 1), (1, 2), (2, 3), (3, 0)], "anti": [(0, 2)]},
+                    {"k": 4, "edges": [(0, 1), (1, 2), (2, 3)], "anti": [(0, 2)]},
+                    {"k": 3, "edges": [(0, 1), (1, 2)], "av": [[1]]},
+                    {"k": 2, "edges": [(0, 1)], "av": [[0, 1]]},
+                    {"k": 3, "edges": [(0, 1), (1, 2), (0, 2)], "av": [[0, 2]]},
+                    {"k": 3, "edges": [(0, 1), (1, 2)], "av": [[0, 2], [1]]},
+                    {"k": 4, "edges": [(0, 1), (0, 2), (0, 3)], "av": [[1, 2, 3]]},
+                    {"k": 5, "edges": [(0, 1), (1, 2), (2, 3), (3, 4)], "av": [[0, 4]]}])
+
+
+@pytest.mark.parametrize("pi", range(len(PLAN_PATTERNS)))
+def test_core_is_minimum_connected_cover(pi):
+    spec = PLAN_PATTERNS[pi]
+    info = pg.plan_pattern(spec).info()
+    assert info["core_size"] == _min_connected_cover_size(spec)
+
+
+@pytest.mark.parametrize("pi", range(len(PLAN_PATTERNS)))
+@pytest.mark.parametrize("mode", [pg.PG_PLAN_LINEAR_EXT, pg.PG_PLAN_PARTIAL_ORDER])
+def test_programs_count_like_oracle(pi, mode, orc):
+    spec = PLAN_PATTERNS[pi]
+    plan = pg.plan_pattern(spec, mode=mode)
+    progs = plan.programs()
+    for seed in (1, 2):
+        g = gg.gnp(9, 0.5, seed=seed + 10 * pi)
+        expect = orc.count(orc.Graph.from_tuple(g), spec)
+        assert interp_count(g, progs) == expect, (spec, seed)
+
+
+def _orbit_key(row, auts):
+    return min(tuple(row[p[i]] for i in range(len(row))) for p in auts)
+
+
+def _typed_auts(spec):
+    k = spec["k"]
+    out = []
+    for pm in itertools.permutations(range(k)):
+        sub = {"k": k, "edges": spec["edges"], "anti": spec.get("anti"), "induced": spec.get("induced"),
+               "av": spec.get("av"), "labels": spec.get("labels")}
+        img = [None] * k
+        for i in range(k):
+            img[i] = pm[i]
+        if brute.is_valid_map(_pattern_as_graph(sub), None, sub, tuple(img)):
+            out.append(pm)
+    return out
+
+
+def _pattern_as_graph(spec):
+    k = spec["k"]
+    adj = [set() for _ in range(k)]
+    for a, b in spec["edges"]:
+        adj[a].add(b)
+        adj[b].add(a)
+    return adj
+
+
+@pytest.mark.parametrize("pi", range(len(PLAN_PATTERNS)))
+def test_enum_programs_one_per_orbit(pi, orc):
+    spec = PLAN_PATTERNS[pi]
+    if spec.get("av"):
+        pytest.skip("orbit keys below only cover patterns without anti-vertices")
+    plan = pg.plan_pattern(spec)
+    progs = plan.programs(enum_mode=True)
+    g = gg.gnp(8, 0.55, seed=pi)
+    rows = interp_enumerate(g, progs, spec["k"])
+    adj = brute._adj_sets(*g)
+    for r in rows:
+        assert brute.is_valid_map(adj, None, spec, r)
+    auts = [p for p in itertools.permutations(range(spec["k"]))
+            if all(((p[b] in _pattern_as_graph(spec)[p[a]]) == (b in _pattern_as_graph(spec)[a]))
+                   for a, b in itertools.combinations(range(spec["k"]), 2))]
+    # orbits under the typed automorphisms: compare via the oracle's count
+    assert len(rows) == orc.count(orc.Graph.from_tuple(g), spec)
+    assert len(set(rows)) == len(rows)
+    if not spec.get("anti") and not spec.get("induced"):
+        keys = {_orbit_key(r, auts) for r in rows}
+        assert len(keys) == len(rows)
+
+
+def test_labelled_programs(orc):
+    rng = np.random.Generator(np.random.PCG64(5))
+    for seed in range(4):
+        g = gg.gnp(9, 0.55, seed=seed)
+        lab = rng.integers(0, 2, 9).astype(np.int16)
+        og = orc.Graph.from_tuple(g, lab)
+        for spec in ({"k": 3, "edges": [(0, 1), (1, 2)], "labels": [0, 1, 0]},
+                     {"k": 3, "edges": [(0, 1), (1, 2), (0, 2)], "labels": [1, 1, 0]},
+                     {"k": 4, "edges": [(0, 1), (0, 2), (0, 3)], "labels": [1, 0, 0, 1]},
+                     {"k": 3, "edges": [(0, 1), (1, 2)], "av": [[0, 2]], "labels": [0, -1, 1], "av_labels": [1]}):
+            assert interp_count(g, pg.plan_pattern(spec).programs(), labels=lab) == orc.count(og, spec)
+
+
+def test_partial_order_gives_one_map_per_orbit(orc):
+    """Grochow-Kellis: among the valid maps, exactly count() satisfy the
+    partial order (the PRG-U relation read backwards)."""
+    g = gg.gnp(8, 0.6, seed=3)
+    adj = brute._adj_sets(*g)
+    for spec in [DIAMOND, pt.clique(4), pt.star(4), pt.chain(4), pt.P8_INDUCED_DIAMOND, pt.P7_TRIANGLE_NO_K4,
+                 {"k": 4, "edges": [(0, 1), (1, 2), (2, 3), (3, 0)], "anti": [(0, 2)]}]:
+        order = pg.plan_pattern(spec).info()["order"]
+        maps = brute.canonical_maps(g, spec)
+        kept = [m for m in maps if all(m[a] < m[b] for a, b in order)]
+        assert len(kept) == orc.count(orc.Graph.from_tuple(g), spec)
+        assert len(maps) == len(kept) * orc.aut(spec)
+
+
+@pytest.mark.parametrize("bad", [
+    {"k": 1, "edges": []},
+    {"k": 17, "edges": [(i, i + 1) for i in range(16)]},
+    {"k": 4, "edges": [(0, 1), (2, 3)]},                       # disconnected
+    {"k": 3, "edges": [(0, 1), (1, 2)], "anti": [(0, 1)]},     # edge and anti-edge
+    {"k": 3, "edges": [(0, 1), (0, 5)]},                       # id out of range
+    {"k": 3, "edges": [(0, 1), (1, 2)], "av": [[]]},           # anti-vertex without anti-edges
+])
+def test_invalid_patterns_rejected(bad):
+    with pytest.raises(pg.PGError) as e:
+        pg.plan_pattern(bad)
+    assert e.value.status == pg.PG_EINVAL
+
+
+def test_anti_vertex_with_true_edge_rejected():
+    d, keep = pg.pattern_desc({"k": 3, "edges": [(0, 1), (1, 2)], "av": [[0]]})
+    d.edges[2].type = pg.PG_EDGE
+    import ctypes
+    h = ctypes.c_void_p()
+    assert pg.lib().pg_plan_pattern(ctypes.byref(d), ctypes.byref(h)) == pg.PG_EINVAL
