@@ -74,6 +74,8 @@ def _L():
         lib.orc_count.argtypes = [vp, ctypes.POINTER(_Pattern), ctypes.c_int, u64p, u64p, u64p]
         lib.orc_valid_maps.restype = ctypes.c_int
         lib.orc_valid_maps.argtypes = [vp, ctypes.POINTER(_Pattern), ctypes.c_int, u64p, u64p]
+        lib.orc_valid_maps_roots.restype = ctypes.c_int
+        lib.orc_valid_maps_roots.argtypes = [vp, ctypes.POINTER(_Pattern), ctypes.c_int, vp, i64, u64p, u64p]
         lib.orc_esu_census.restype = ctypes.c_int
         lib.orc_esu_census.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, vp]
         lib.orc_noninduced4.restype = ctypes.c_int
@@ -194,6 +196,17 @@ def valid_maps(g: Graph, spec, threads: int | None = None) -> int:
     lo, hi = ctypes.c_uint64(), ctypes.c_uint64()
     rc = _L().orc_valid_maps(g._h, ctypes.byref(_to_struct(spec)), threads or default_threads(),
                              ctypes.byref(lo), ctypes.byref(hi))
+    if rc:
+        raise ValueError("pattern is not connected by true edges")
+    return (hi.value << 64) | lo.value
+
+
+def valid_maps_from(g: Graph, spec, roots, threads: int | None = None) -> int:
+    """Valid maps whose pattern vertex 0 is mapped into ``roots``."""
+    r = np.ascontiguousarray(roots, dtype=np.int32)
+    lo, hi = ctypes.c_uint64(), ctypes.c_uint64()
+    rc = _L().orc_valid_maps_roots(g._h, ctypes.byref(_to_struct(spec)), threads or default_threads(),
+                                   r.ctypes.data, len(r), ctypes.byref(lo), ctypes.byref(hi))
     if rc:
         raise ValueError("pattern is not connected by true edges")
     return (hi.value << 64) | lo.value

@@ -217,6 +217,8 @@ typedef struct {
     const orc_pattern *p;
     int order[16];    /* BFS order over true edges */
     int parent[16];   /* an earlier position that is a true neighbour */
+    const int32_t *roots;  /* NULL: every vertex is a start vertex */
+    int64_t n_roots;
     atomic_int_fast64_t cursor;
     u128 total;
     pthread_mutex_t mu;
@@ -282,7 +284,8 @@ static void *match_worker(void *arg) {
     u128 local = 0;
     for (;;) {
         int64_t v = atomic_fetch_add(&J->cursor, 1);
-        if (v >= J->g->n) break;
+        if (v >= J->n_roots) break;
+        if (J->roots) v = J->roots[v];
         int u0 = J->order[0];
         if (p->label[u0] != -1 && (!J->g->label || J->g->label[v] != p->label[u0])) continue;
         img[u0] = (int32_t)v;
@@ -294,14 +297,19 @@ static void *match_worker(void *arg) {
     return NULL;
 }
 
-/* Number of valid maps of p into g (see the file header).  Returns -1 if the
- * regular vertices are not connected by true edges. */
-int orc_valid_maps(const orc_graph *g, const orc_pattern *p, int nthreads, uint64_t *lo,
-                   uint64_t *hi) {
+/* Number of valid maps of p into g whose first pattern vertex (vertex 0)
+ * is mapped to one of roots[0..n_roots) (roots == NULL: any vertex).  Used
+ * whole by orc_count and on a bounded sample of start vertices to time the
+ * oracle.  Returns -1 if the regular vertices are not connected by true
+ * edges. */
+int orc_valid_maps_roots(const orc_graph *g, const orc_pattern *p, int nthreads, const int32_t *roots,
+                         int64_t n_roots, uint64_t *lo, uint64_t *hi) {
     match_job J;
     memset(&J, 0, sizeof(J));
     J.g = g;
     J.p = p;
+    J.roots = roots;
+    J.n_roots = roots ? n_roots : g->n;
     /* BFS over true edges from regular vertex 0 */
     int seen[16] = {0};
     int head = 0, tail = 0;
@@ -329,6 +337,12 @@ int orc_valid_maps(const orc_graph *g, const orc_pattern *p, int nthreads, uint6
     *lo = (uint64_t)J.total;
     *hi = (uint64_t)(J.total >> 64);
     return 0;
+}
+
+/* Number of valid maps of p into g (see the file header). */
+int orc_valid_maps(const orc_graph *g, const orc_pattern *p, int nthreads, uint64_t *lo,
+                   uint64_t *hi) {
+    return orc_valid_maps_roots(g, p, nthreads, NULL, 0, lo, hi);
 }
 
 /* count(G, p) = |valid maps| / |Aut_t(p)|.  Returns 0 on success, -1 for a

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -69,7 +70,7 @@ struct pg_graph {
     size_t trie_bytes = 0;
     unsigned long long *ctl = nullptr;  // counts[64], cursor, emit_ctr, bytes, flags[2]
     // cached trie of the last launch
-    std::vector<const pg_plan *> trie_key;
+    std::vector<uint64_t> trie_key;
     bool trie_emit = false;
     pg::Trie trie;
     bool trie_valid = false;
@@ -311,7 +312,9 @@ pg_status pg_plan_pattern_ex(const pg_pattern_desc *p, const pg_plan_options *op
         if (opt)
             for (int i = 0; i < 7; i++)
                 if (opt->reserved[i]) { set_error("pg_plan_options.reserved must be zero"); return PG_EINVAL; }
+        static std::atomic<uint64_t> next_uid{1};
         std::unique_ptr<pg_plan> plan(new pg_plan());
+        plan->uid = next_uid.fetch_add(1);
         std::string err;
         pg_status st = pg::compile_plan(p, opt, &plan->impl, &err);
         if (st) {
@@ -394,7 +397,8 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     const bool emit = la.mode == pg::kModeEmit;
 
     // program trie (cached for a repeated plan list)
-    std::vector<const pg_plan *> key(plans, plans + n_plans);
+    std::vector<uint64_t> key;
+    for (int i = 0; i < n_plans; i++) key.push_back(plans[i]->uid);
     if (!g->trie_valid || g->trie_key != key || g->trie_emit != emit) {
         std::vector<const pg::PlanImpl *> impls;
         for (int i = 0; i < n_plans; i++) impls.push_back(&plans[i]->impl);
@@ -405,6 +409,7 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     }
     const pg::Trie &T = g->trie;
     if (T.max_level > pg::kMaxLevels) { set_error("plan too deep"); return PG_EUNSUPPORTED; }
+    if (!T.consistent) { set_error("internal: program trie lost a program"); return PG_EUNSUPPORTED; }
 
     // upload the trie: nodes | avs | roots
     size_t nb = T.nodes.size() * sizeof(pg::Node), ab = T.avs.size() * sizeof(pg::AVCheck),

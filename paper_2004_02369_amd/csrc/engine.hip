@@ -687,10 +687,12 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
         if (lane == 0) t0 = atomicAdd(P.cursor, (unsigned long long)P.chunk);
         t0 = __shfl(t0, 0);
         if ((long long)t0 >= total_tasks) break;
-        const bool edge_phase = (long long)t0 < P.n_etasks;
-        const long long t_end = edge_phase ? min((long long)t0 + P.chunk, P.n_etasks)
-                                           : min((long long)t0 + P.chunk, total_tasks);
-        for (long long tb = (long long)t0; tb < t_end; tb += kP) {
+        const long long c_end = min((long long)t0 + P.chunk, total_tasks);
+        for (long long tb = (long long)t0; tb < c_end;) {
+            // edge tasks occupy [0, n_etasks), vertex tasks the rest; a chunk
+            // may straddle the boundary
+            const bool edge_phase = tb < P.n_etasks;
+            const long long t_end = edge_phase ? min(c_end, P.n_etasks) : c_end;
             const int np = (int)min((long long)kP, t_end - tb);
             for (int r = 0; r < P.n_roots; r++) {
                 const int rid = uni(P.roots[r]);
@@ -749,6 +751,7 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
                 }
                 wsync();
             }
+            tb += np;
         }
     }
     wsync();

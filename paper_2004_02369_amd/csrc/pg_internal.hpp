@@ -93,6 +93,7 @@ struct Trie {
     int32_t max_level = 0;        // deepest level index + 1
     bool has_vertex_root = false;
     bool has_edge_root = false;
+    bool consistent = false;      // one leaf per program
 };
 
 Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit);
@@ -107,4 +108,5 @@ void set_error(const std::string &msg);
 
 struct pg_plan {
     pg::PlanImpl impl;
+    uint64_t uid = 0;  // unique per plan object (cache key; addresses get reused)
 };

@@ -767,14 +767,19 @@ Node blank_node() {
 Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
     std::vector<HostNode> H;
     std::vector<int> roots;
-    auto child = [&](std::vector<int> &kids, HostNode &&hn) -> int {
+    // find or add a child of `parent` (-1: a root); H may reallocate, so the
+    // parent's child list is looked up again after the insertion
+    auto child = [&](int parent, HostNode &&hn) -> int {
+        const std::vector<int> &kids = parent < 0 ? roots : H[parent].children;
         for (int c : kids)
             if (H[c].key == hn.key) return c;
         H.push_back(std::move(hn));
-        int id = (int)H.size() - 1;
-        kids.push_back(id);
+        const int id = (int)H.size() - 1;
+        if (parent < 0) roots.push_back(id);
+        else H[parent].children.push_back(id);
         return id;
     };
+    size_t n_programs = 0;
     int max_level = 0;
     for (size_t pi = 0; pi < plans.size(); pi++) {
         const auto &progs = emit ? plans[pi]->enum_progs : plans[pi]->count_progs;
@@ -790,7 +795,8 @@ Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
             for (int x = 0; x <= r.n.level; x++)
                 for (const AVCheck &c : p.lev[x].avs) r.avs.push_back(c);
             r.key = node_key(r.n, r.avs);
-            int cur = child(roots, std::move(r));
+            int cur = child(-1, std::move(r));
+            n_programs++;
             for (int x = H[cur].n.level + 1; x <= F; x++) {
                 const Level &L = p.lev[x];
                 HostNode h;
@@ -809,8 +815,7 @@ Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
                     for (int y = 0; y <= F; y++) h.n.pv[y] = (int8_t)p.lev[y].pv;
                 }
                 h.key = node_key(h.n, h.avs);
-                int nxt = child(H[cur].children, std::move(h));
-                cur = nxt;
+                cur = child(cur, std::move(h));
             }
         }
     }
@@ -852,6 +857,11 @@ Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
             else T.has_edge_root = true;
         }
     }
+    // every program ends in its own leaf (count programs are merged before,
+    // so two leaves never share a key)
+    size_t leaves = 0;
+    for (const Node &n : T.nodes) leaves += (n.kind == kCount || n.kind == kEmit) ? 1 : 0;
+    T.consistent = leaves == n_programs;
     return T;
 }
 

@@ -1,0 +1,82 @@
+"""GPU parity at the benchmark workloads' full sizes, against exact counts the
+oracle wrote to tests/golden/expected.json (make_golden.py), in the launch
+configuration bench.py times (default grid and chunk)."""
+import json
+import os
+import sys
+
+import pytest
+
+from paper_2004_02369_amd import graphgen as gg
+from paper_2004_02369_amd import patterns as pt
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+with open(os.path.join(HERE, "golden", "expected.json")) as f:
+    GOLD = json.load(f)["workloads"]
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2004_02369_amd import pg as _pg
+    _pg.lib()
+    return _pg
+
+
+def _motif_expect(orc, gold_block, k, specs):
+    return [gold_block[str(orc.canonical_of_edges(k, s["edges"]))]["count"] for s in specs]
+
+
+def test_er_2k_20k_one_pattern_per_launch(pg, orc):
+    w = GOLD["er_2k_20k"]
+    say("er_2k_20k triangle / wedge / 4-clique, one per launch")
+    G = pg.load_graph(*gg.workload("er_2k_20k"), device=0)
+    assert G.m == w["m"]
+    assert pg.count(G, pg.plan_pattern(pt.clique(3))) == w["triangle"]
+    assert pg.count(G, pg.plan_pattern(pt.star(3))) == w["wedge"] == w["sum_c_d_2"]
+    assert pg.count(G, pg.plan_pattern(pt.star(3, induced=True))) == w["wedge_induced"]
+    assert w["wedge_induced"] == w["wedge"] - 3 * w["triangle"]
+    assert pg.count(G, pg.plan_pattern(pt.clique(4))) == w["clique4"]
+    assert pg.count(G, pg.plan_pattern(pt.clique(5))) == w["clique5"]
+    specs = pt.all_vertex_induced(4)
+    assert pg.count(G, [pg.plan_pattern(s) for s in specs]) == _motif_expect(orc, w["induced4"], 4, specs)
+
+
+def test_chunglu_100k_1m_six_motifs_batched(pg, orc):
+    w = GOLD["chunglu_100k_1m"]
+    say("chunglu_100k_1m 6 induced 4-motifs batched")
+    G = pg.load_graph(*gg.workload("chunglu_100k_1m"), device=0)
+    assert G.m == w["m"] and G.d_max == w["d_max"]
+    specs = pt.all_vertex_induced(4)
+    plans = [pg.plan_pattern(s) for s in specs]
+    want = _motif_expect(orc, w["induced4"], 4, specs)
+    assert pg.count(G, plans) == want
+    say("chunglu_100k_1m triangle / wedge")
+    assert pg.count(G, [pg.plan_pattern(pt.clique(3)), pg.plan_pattern(pt.star(3))]) == \
+        [w["triangle"], w["sum_c_d_2"]]
+
+
+def test_rmat_small_22_plans(pg, orc):
+    w = GOLD["rmat9_2k"]
+    say("rmat9_2k 21 induced 5-motifs + K5 batched")
+    G = pg.load_graph(*gg.rmat(**w["params"]), device=0)
+    assert G.m == w["m"]
+    specs = pt.all_vertex_induced(5) + [pt.clique(5)]
+    plans = [pg.plan_pattern(s) for s in specs]
+    got = pg.count(G, plans)
+    want = _motif_expect(orc, w["induced5"], 5, specs[:-1]) + [w["clique5"]]
+    assert got == want
+    # K5 is one of the 21 induced motifs: both must agree
+    assert got[-1] == got[-2]
+    # invariant row: sum_Q c(K_{1,4}, Q) I_Q = sum_v C(d_v, 4)
+    inv = orc.star_row_invariant(5, {orc.canonical_of_edges(5, s["edges"]): c for s, c in zip(specs[:-1], got)})
+    assert inv == w["sum_c_d_4"]
+    # batched = one launch per plan
+    assert [pg.count(G, p) for p in plans] == got
