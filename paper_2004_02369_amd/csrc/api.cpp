@@ -52,11 +52,16 @@ struct pg_graph {
     int32_t d_max = 0;
     int32_t device = 0;
     int32_t n_cu = 0;
+    int32_t blocks_per_cu = 0;  // resident match_kernel wavefronts per CU
     bool labelled = false;
     std::vector<int32_t> perm;  // rank -> original id
     // device arrays
     int64_t *rp = nullptr;
     int32_t *col = nullptr;
+    int32_t *up = nullptr;
+    uint32_t *hub_bits = nullptr;  // dense adjacency bitmaps of ranks hub_start..n-1
+    int32_t hub_start = 0;
+    int64_t hub_words = 0;
     int16_t *lab = nullptr;
     int32_t *dperm = nullptr;
     int32_t *tsrc = nullptr;
@@ -78,6 +83,8 @@ struct pg_graph {
     ~pg_graph() {
         dfree(rp);
         dfree(col);
+        dfree(up);
+        dfree(hub_bits);
         dfree(lab);
         dfree(dperm);
         dfree(tsrc);
@@ -89,6 +96,9 @@ struct pg_graph {
 };
 
 namespace {
+
+constexpr int64_t kHubMinDegree = 128;
+constexpr int64_t kHubBudgetBytes = int64_t(1) << 30;
 
 constexpr int kCtlCounts = 0;
 constexpr int kCtlCursor = 64;
@@ -222,6 +232,10 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         keys.clear();
         keys.shrink_to_fit();
         for (int32_t r = 0; r < n; r++) std::sort(col.begin() + rp[r], col.begin() + rp[r + 1]);
+        // split of each row into lower and upper neighbours (degree-oriented part)
+        std::vector<int32_t> up(n);
+        for (int32_t r = 0; r < n; r++)
+            up[r] = (int32_t)(std::lower_bound(col.begin() + rp[r], col.begin() + rp[r + 1], r) - (col.begin() + rp[r]));
 
         // 4. root edge tasks u < v, costliest first (Sec. 5.2: start with the
         //    highest-degree vertices); cost estimate d(u) + d(v)
@@ -258,9 +272,30 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         hipDeviceProp_t prop;
         PG_HIP(hipGetDeviceProperties(&prop, dev));
         g->n_cu = prop.multiProcessorCount;
+        g->blocks_per_cu = pg::match_blocks_per_cu();
         pg_status st;
         if ((st = upload(&g->rp, rp, &g->device_bytes))) return st;
         if ((st = upload(&g->col, col, &g->device_bytes))) return st;
+        if ((st = upload(&g->up, up, &g->device_bytes))) return st;
+        // hub rows also as dense bitmaps: the highest-degree vertices (rank
+        // order is degree order) with degree >= kHubMinDegree, within a budget
+        {
+            const int64_t words = ((int64_t)n + 31) / 32;
+            int32_t hs = n;
+            while (hs > 0 && rp[hs] - rp[hs - 1] >= kHubMinDegree &&
+                   (int64_t)(n - hs + 1) * words * 4 <= kHubBudgetBytes)
+                hs--;
+            g->hub_start = hs;
+            g->hub_words = words;
+            if (hs < n) {
+                std::vector<uint32_t> bits((size_t)(n - hs) * (size_t)words, 0u);
+                for (int32_t r = hs; r < n; r++) {
+                    uint32_t *b = bits.data() + (size_t)(r - hs) * (size_t)words;
+                    for (int64_t e = rp[r]; e < rp[r + 1]; e++) b[col[e] >> 5] |= 1u << (col[e] & 31);
+                }
+                if ((st = upload(&g->hub_bits, bits, &g->device_bytes))) return st;
+            }
+        }
         if ((st = upload(&g->dperm, perm, &g->device_bytes))) return st;
         if ((st = upload(&g->tsrc, tsrc, &g->device_bytes))) return st;
         if ((st = upload(&g->tdst, tdst, &g->device_bytes))) return st;
@@ -431,7 +466,8 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     PG_HIP(hipMemcpyAsync(g->trie_buf, host.data(), need, hipMemcpyHostToDevice, s));
 
     // launch shape
-    int grid = cfg && cfg->grid_waves ? cfg->grid_waves : g->n_cu * 8;
+    // persistent grid: exactly the wavefronts that can be resident at once
+    int grid = cfg && cfg->grid_waves ? cfg->grid_waves : g->n_cu * g->blocks_per_cu;
     const long long n_et = T.has_edge_root ? (long long)g->m : 0;
     const long long n_vt = T.has_vertex_root ? (long long)g->n : 0;
     int chunk = cfg && cfg->chunk ? cfg->chunk : 64;
@@ -455,6 +491,10 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     std::memset(&P, 0, sizeof(P));
     P.rp = g->rp;
     P.col = g->col;
+    P.up = g->up;
+    P.hub_bits = g->hub_bits;
+    P.hub_words = g->hub_words;
+    P.hub_start = g->hub_start;
     P.lab = g->lab;
     P.perm = g->dperm;
     P.tsrc = g->tsrc;

@@ -17,12 +17,13 @@
 //    compacts the survivors in order, so the set stays sorted;
 //  * a count node completes the non-core vertices by set size (Sec. 5.1
 //    completes them by intersections; here only |S| is needed): its work is
-//    flattened over up to 64 prefixes at once -- per prefix, one or more
-//    segments of driver elements are laid end to end and the wave's lanes
-//    walk the concatenation, so short rows do not leave lanes idle.  When
-//    the only positive operand is long and the differences are short the
-//    count is taken by complement, |P| - |P & (D1 u D2 ...)|, driven by the
-//    short difference rows;
+//    flattened over up to 64 prefixes at once -- each lane sets up one
+//    prefix and emits one or more segments of driver elements, a wave
+//    prefix scan lays the segments end to end, and the lanes walk the
+//    concatenation, so short rows do not leave lanes idle.  When the only
+//    positive operand is long and the differences are short the count is
+//    taken by complement, |P| - |P & (D1 u D2 ...)|, driven by the short
+//    difference rows;
 //  * counts are reduced per wave in 64-bit and added to the per-plan
 //    counters once per wave at exit.
 #include <hip/hip_runtime.h>
@@ -34,43 +35,53 @@
 
 namespace pg {
 
-constexpr int kP = 64;       // prefixes per flattened batch (one per lane)
-constexpr int kSegPerPrefix = 3;
-constexpr int kSeg = kP * kSegPerPrefix;
-constexpr int kBaseOp = 31;  // operand id of the base set
+constexpr int kP = 64;        // prefixes per flattened batch (one per lane)
+constexpr int kMaxDiffB = 3;  // complement counting handles up to this many difference rows
+constexpr int kSeg = kP * kMaxDiffB;
+constexpr int kBaseOp = 31;   // operand id of the base set
 
 struct Lds {
+    // the fixed assignment (levels matched so far) and their rows
     int32_t m[kMaxLevels];
     long long roff[kMaxLevels];
     int32_t rlen[kMaxLevels];
+    int32_t rup[kMaxLevels];      // index of the first neighbour above the row's owner
+    int32_t cur_idx[kMaxLevels];  // index of m[level] in that level's materialised set
     int32_t set_len[kMaxLevels];
     int32_t st_node[kMaxLevels];
     int32_t st_idx[kMaxLevels];
     int32_t st_child[kMaxLevels];
     // root tasks of the current batch
     int32_t tu[kP], tv[kP];
-    // prefix batch: values of the (at most two) varying levels
+    // prefix batch: values and rows of the (at most two) varying levels
     int32_t pv0[kP], pv1[kP];
     long long po0[kP], po1[kP];
     int32_t pl0[kP], pl1[kP];
-    int32_t plo[kP], phi[kP];
+    int32_t pu0[kP], pu1[kP];
+    int32_t pidx[kP];             // index of the prefix in its own set (set batches)
     const int32_t *bptr[kP];
     int32_t blen[kP];
     const int32_t *p1ptr[kP];
     int32_t p1len[kP];
-    int32_t pmode[kP];       // -1 skip, 0 direct, 1 complement
+    int32_t p1own[kP];            // owner of the P1 row, -1 for a set
+    int32_t pmode[kP];            // -1 skip, 0 direct, 1 complement
     int32_t pdrv[kP];
     uint32_t pcnt[kP];
     int32_t pconst[kP];
     int32_t seg_start[kSeg + 1];
     int16_t seg_prefix[kSeg];
-    int16_t seg_op[kSeg];
     const int32_t *seg_ptr[kSeg];
+    int32_t seg_own[kSeg];
     unsigned long long acc[kMaxPlansPerLaunch];
-    int32_t nseg;
-    int32_t total;
     int32_t stop;
     unsigned long long bytes;
+};
+
+struct RowRef {
+    const int32_t *p;
+    int32_t n;
+    int32_t up;     // index of the first element above `owner`
+    int32_t owner;
 };
 
 __device__ __forceinline__ void wsync() { __syncthreads(); }
@@ -97,15 +108,22 @@ __device__ __forceinline__ bool contains(const int32_t *__restrict__ a, int32_t 
     return i < n && a[i] == key;
 }
 
-// restrict sorted a[0, n) to values in (lo, hi): returns begin, sets len
-__device__ __forceinline__ int32_t restrict_range(const int32_t *a, int32_t n, int32_t lo, int32_t hi,
-                                                  int32_t *len) {
-    if (lo >= hi - 1 || n == 0) {
+// restrict a row to values in (lo, hi); a bound equal to the row's owner is
+// the precomputed split between its lower and upper neighbours
+__device__ __forceinline__ int32_t restrict_row(const RowRef &r, int32_t lo, int32_t hi, int32_t *len) {
+    if (lo >= hi - 1 || r.n == 0) {
         *len = 0;
         return 0;
     }
-    int32_t b = (lo < 0) ? 0 : lower_bound(a, n, lo + 1);
-    int32_t e = (hi == INT_MAX) ? n : lower_bound(a, n, hi);
+    int32_t b, e;
+    if (lo < 0) b = 0;
+    else if (lo == r.owner) b = r.up;
+    else if (lo > r.owner) b = r.up + lower_bound(r.p + r.up, r.n - r.up, lo + 1);
+    else b = lower_bound(r.p, r.up, lo + 1);
+    if (hi == INT_MAX) e = r.n;
+    else if (hi == r.owner) e = r.up;
+    else if (hi > r.owner) e = r.up + lower_bound(r.p + r.up, r.n - r.up, hi);
+    else e = lower_bound(r.p, r.up, hi);
     *len = e > b ? e - b : 0;
     return b;
 }
@@ -125,6 +143,38 @@ __device__ __forceinline__ unsigned long long choose(unsigned long long n, int j
     return r;
 }
 
+// exclusive prefix sum over the wave; *tot receives the wave total
+__device__ __forceinline__ int wave_scan_excl(int x, int lane, int *tot) {
+    int inc = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(inc, off, 64);
+        if (lane >= off) inc += y;
+    }
+    *tot = __shfl(inc, 63, 64);
+    return inc - x;
+}
+
+// membership of e in the row of r.owner: one load for a hub (dense bitmap),
+// a binary search otherwise
+__device__ __forceinline__ bool in_row(const KParams &P, const RowRef &r, int32_t e) {
+    if (r.owner >= P.hub_start) {
+        const uint32_t w = P.hub_bits[(long long)(r.owner - P.hub_start) * P.hub_words + (e >> 5)];
+        return (w >> (e & 31)) & 1u;
+    }
+    return contains(r.p, r.n, e);
+}
+
+// membership in a sorted range whose elements are a row's (owner >= 0) or a
+// materialised set's (owner < 0); the caller knows e lies in the range's bounds
+__device__ __forceinline__ bool in_range(const KParams &P, const int32_t *p, int32_t n, int32_t owner, int32_t e) {
+    if (owner >= P.hub_start) {
+        const uint32_t w = P.hub_bits[(long long)(owner - P.hub_start) * P.hub_words + (e >> 5)];
+        return (w >> (e & 31)) & 1u;
+    }
+    return contains(p, n, e);
+}
+
 struct Ctx {
     const KParams &P;
     Lds &L;
@@ -137,102 +187,58 @@ struct Ctx {
     __device__ __forceinline__ int32_t *setbuf(int level) const { return buf0 + (long long)(level - 2) * P.set_cap; }
 
     __device__ __forceinline__ int32_t val(int y, int l) const {
+        if (l < 0) return L.m[y];
         if (y == vl0) return L.pv0[l];
         if (y == vl1) return L.pv1[l];
         return L.m[y];
     }
-    __device__ __forceinline__ void row(int y, int l, const int32_t **p, int32_t *n) const {
-        if (y == vl0) {
-            *p = P.col + L.po0[l];
-            *n = L.pl0[l];
-        } else if (y == vl1) {
-            *p = P.col + L.po1[l];
-            *n = L.pl1[l];
+
+    __device__ __forceinline__ RowRef row(int y, int l) const {
+        RowRef r;
+        if (l >= 0 && y == vl0) {
+            r.p = P.col + L.po0[l];
+            r.n = L.pl0[l];
+            r.up = L.pu0[l];
+            r.owner = L.pv0[l];
+        } else if (l >= 0 && y == vl1) {
+            r.p = P.col + L.po1[l];
+            r.n = L.pl1[l];
+            r.up = L.pu1[l];
+            r.owner = L.pv1[l];
         } else {
-            *p = P.col + L.roff[y];
-            *n = L.rlen[y];
+            r.p = P.col + L.roff[y];
+            r.n = L.rlen[y];
+            r.up = L.rup[y];
+            r.owner = L.m[y];
         }
+        return r;
     }
 
-    // anti-vertex check for candidate e at level x under prefix l (l < 0:
-    // the fixed assignment only): the sets N(m(a)) \ m(xmask[a]) over the
-    // anti-vertex's neighbour levels a must have an empty intersection.
-    __device__ bool av_pass(const AVCheck &c, int x, int l, int32_t e) const {
-        const int32_t *best = nullptr;
-        int32_t best_n = INT_MAX;
-        int best_a = -1;
-        for (int a = 0; a < kMaxLevels; a++) {
-            if (!(c.nbr >> a & 1u)) continue;
-            int32_t v = (a == x) ? e : (l >= 0 ? val(a, l) : L.m[a]);
-            const int32_t *p = P.col + P.rp[v];
-            int32_t n = (int32_t)(P.rp[v + 1] - P.rp[v]);
-            if (n < best_n) {
-                best_n = n;
-                best = p;
-                best_a = a;
-            }
-        }
-        for (int32_t i = 0; i < best_n; i++) {
-            int32_t w = best[i];
-            if (c.label >= 0 && (P.lab == nullptr || P.lab[w] != c.label)) continue;
-            bool in_all = true;
-            for (int a = 0; a < kMaxLevels && in_all; a++) {
-                if (!(c.nbr >> a & 1u)) continue;
-                // w must not be the image of a true neighbour of a
-                uint32_t xm = c.xmask[a];
-                for (int y = 0; y < kMaxLevels && in_all; y++) {
-                    if (!(xm >> y & 1u)) continue;
-                    int32_t vy = (y == x) ? e : (l >= 0 ? val(y, l) : L.m[y]);
-                    if (vy == w) in_all = false;
-                }
-                if (!in_all || a == best_a) continue;
-                int32_t v = (a == x) ? e : (l >= 0 ? val(a, l) : L.m[a]);
-                if (!contains(P.col + P.rp[v], (int32_t)(P.rp[v + 1] - P.rp[v]), w)) in_all = false;
-            }
-            if (in_all) return false;
-        }
-        return true;
+    __device__ __forceinline__ RowRef vrow(int32_t v) const {
+        RowRef r;
+        long long o = P.rp[v];
+        r.p = P.col + o;
+        r.n = (int32_t)(P.rp[v + 1] - o);
+        r.up = P.up[v];
+        r.owner = v;
+        return r;
     }
+
+    __device__ bool av_pass(const AVCheck &c, int x, int l, int32_t e) const;
 
     // direct test of candidate e of node N at level x (driver operand drv
-    // already satisfied), prefix l or -1
-    __device__ bool test_direct(const Node &N, int x, int l, int drv, int32_t e, const int32_t *bp,
-                                int32_t bn) const {
+    // already satisfied), prefix l or -1 (fixed assignment, base range bp/bn)
+    __device__ __forceinline__ bool test_direct(const Node &N, int x, int l, int drv, int32_t e, const int32_t *bp,
+                                                int32_t bn) const {
         bool ok = true;
         if (N.base >= 0 && drv != kBaseOp) ok = contains(bp, bn, e);
-        uint32_t ti = N.t_isect;
-        while (ti && ok) {
+        for (uint32_t ti = N.t_isect; ti && ok; ti &= ti - 1) {
             int y = __builtin_ctz(ti);
-            ti &= ti - 1;
             if (y == drv) continue;
-            const int32_t *p;
-            int32_t n;
-            if (l >= 0) row(y, l, &p, &n);
-            else {
-                p = P.col + L.roff[y];
-                n = L.rlen[y];
-            }
-            ok = contains(p, n, e);
+            ok = in_row(P, row(y, l), e);
         }
-        uint32_t td = N.t_diff;
-        while (td && ok) {
-            int y = __builtin_ctz(td);
-            td &= td - 1;
-            const int32_t *p;
-            int32_t n;
-            if (l >= 0) row(y, l, &p, &n);
-            else {
-                p = P.col + L.roff[y];
-                n = L.rlen[y];
-            }
-            ok = !contains(p, n, e);
-        }
-        uint32_t ex = N.excl;
-        while (ex && ok) {
-            int y = __builtin_ctz(ex);
-            ex &= ex - 1;
-            ok = e != (l >= 0 ? val(y, l) : L.m[y]);
-        }
+        for (uint32_t td = N.t_diff; td && ok; td &= td - 1) ok = !in_row(P, row(__builtin_ctz(td), l), e);
+        for (uint32_t ex = N.excl; ex && ok; ex &= ex - 1) ok = e != val(__builtin_ctz(ex), l);
         if (ok && N.label >= 0) ok = P.lab != nullptr && P.lab[e] == N.label;
         for (int i = 0; i < N.av_count && ok; i++) ok = av_pass(P.avs[N.av_begin + i], x, l, e);
         return ok;
@@ -252,31 +258,38 @@ struct Ctx {
         long long bytes = 0;
         if (N.base >= 0) {
             const int32_t *B = setbuf(N.base);
-            int32_t n;
-            int32_t b = restrict_range(B, L.set_len[N.base], lo, hi, &n);
+            const int32_t Bn = L.set_len[N.base];
+            const int32_t cur = L.m[N.base], ci = L.cur_idx[N.base];
+            int32_t b, e;
+            if (lo >= hi - 1) {
+                b = e = 0;
+            } else {
+                b = lo < 0 ? 0 : (lo == cur ? ci + 1 : lower_bound(B, Bn, lo + 1));
+                e = hi == INT_MAX ? Bn : (hi == cur ? ci : lower_bound(B, Bn, hi));
+            }
             bp = B + b;
-            bn = n;
+            bn = e > b ? e - b : 0;
             dptr = bp;
-            dlen = n;
+            dlen = bn;
             drv = kBaseOp;
-            bytes += n;
+            bytes += bn;
         }
         for (uint32_t s = N.t_isect; s; s &= s - 1) {
             int y = __builtin_ctz(s);
+            RowRef r = row(y, -1);
             int32_t n;
-            int32_t b = restrict_range(P.col + L.roff[y], L.rlen[y], lo, hi, &n);
+            int32_t b = restrict_row(r, lo, hi, &n);
             bytes += n;
             if (n < dlen) {
                 dlen = n;
-                dptr = P.col + L.roff[y] + b;
+                dptr = r.p + b;
                 drv = y;
             }
         }
         if (P.run_flags & PG_RUN_COUNT_BYTES) {
             for (uint32_t s = N.t_diff; s; s &= s - 1) {
-                int y = __builtin_ctz(s);
                 int32_t n;
-                restrict_range(P.col + L.roff[y], L.rlen[y], lo, hi, &n);
+                restrict_row(row(__builtin_ctz(s), -1), lo, hi, &n);
                 bytes += n;
             }
             if (lane == 0) L.bytes += 4ull * (unsigned long long)bytes;
@@ -304,26 +317,41 @@ struct Ctx {
 
     // ---------------------------------------------------------------
     // Flattened evaluation of count / emit node N (level x) over np
-    // prefixes already loaded into the batch arrays (pv*, po*, pl*, pmode).
-    __device__ void count_batch(const Node &N, int np) {
+    // prefixes already loaded into the batch arrays (pv*, po*, pl*, pu*,
+    // pmode; pidx when own >= 0: the prefixes are the elements of level
+    // own's set, so a base range bounded by the prefix itself is known).
+    __device__ void count_batch(const Node &N, int np, int own) {
         const int x = N.level;
         const bool emit = N.kind == kEmit;
-        // per-prefix setup: one lane per prefix
+        int my_nseg = 0, my_tot = 0;
+        const int32_t *sp0 = nullptr, *sp1 = nullptr, *sp2 = nullptr;
+        int32_t sl0 = 0, sl1 = 0, sl2 = 0;
+        int so0 = -1, so1 = -1, so2 = -1;  // segment owners (row owner, -1 = a set)
         if (lane < np && L.pmode[lane] >= 0) {
             const int l = lane;
             int32_t lo = -1, hi = INT_MAX;
             for (uint32_t s = N.lo; s; s &= s - 1) lo = max(lo, val(__builtin_ctz(s), l));
             for (uint32_t s = N.hi; s; s &= s - 1) hi = min(hi, val(__builtin_ctz(s), l));
-            L.plo[l] = lo;
-            L.phi[l] = hi;
             const int32_t *dptr = nullptr;
             int32_t dlen = INT_MAX;
-            int drv = -1;
+            int drv = -1, downer = -1;
             long long bytes = 0;
             if (N.base >= 0) {
                 const int32_t *B = setbuf(N.base);
-                int32_t n;
-                int32_t b = restrict_range(B, L.set_len[N.base], lo, hi, &n);
+                const int32_t Bn = L.set_len[N.base];
+                int32_t b, e;
+                if (lo >= hi - 1) {
+                    b = e = 0;
+                } else if (N.base == own) {
+                    const int32_t i = L.pidx[l], pv = L.pv0[l];
+                    b = lo < 0 ? 0 : (lo == pv ? i + 1 : lower_bound(B, Bn, lo + 1));
+                    e = hi == INT_MAX ? Bn : (hi == pv ? i : lower_bound(B, Bn, hi));
+                } else {
+                    const int32_t cur = L.m[N.base], ci = L.cur_idx[N.base];
+                    b = lo < 0 ? 0 : (lo == cur ? ci + 1 : lower_bound(B, Bn, lo + 1));
+                    e = hi == INT_MAX ? Bn : (hi == cur ? ci : lower_bound(B, Bn, hi));
+                }
+                const int32_t n = e > b ? e - b : 0;
                 L.bptr[l] = B + b;
                 L.blen[l] = n;
                 dptr = B + b;
@@ -332,159 +360,202 @@ struct Ctx {
                 bytes += n;
             }
             for (uint32_t s = N.t_isect; s; s &= s - 1) {
-                int y = __builtin_ctz(s);
-                const int32_t *p;
-                int32_t rn;
-                row(y, l, &p, &rn);
+                const int y = __builtin_ctz(s);
+                RowRef r = row(y, l);
                 int32_t n;
-                int32_t b = restrict_range(p, rn, lo, hi, &n);
+                int32_t b = restrict_row(r, lo, hi, &n);
                 bytes += n;
                 if (n < dlen) {
                     dlen = n;
-                    dptr = p + b;
+                    dptr = r.p + b;
                     drv = y;
+                    downer = r.owner;
                 }
             }
             if (dlen == INT_MAX) dlen = 0;
-            int npos = (N.base >= 0 ? 1 : 0) + __builtin_popcount(N.t_isect);
-            int ndiff = __builtin_popcount(N.t_diff);
+            const int npos = (N.base >= 0 ? 1 : 0) + __builtin_popcount(N.t_isect);
+            const int ndiff = __builtin_popcount(N.t_diff);
             bool complement = false;
-            if (!emit && npos == 1 && N.label < 0 && N.av_count == 0 && ndiff >= 1 && ndiff <= kSegPerPrefix &&
-                !(P.run_flags & PG_RUN_NO_MODE_B)) {
+            if (!emit && npos == 1 && N.label < 0 && N.av_count == 0 && ndiff >= 1 && ndiff <= kMaxDiffB &&
+                !(P.run_flags & PG_RUN_NO_MODE_B) && dlen > 0) {
+                // restricted difference rows become the complement's segments
                 long long cost = 0;
-                for (uint32_t s = N.t_diff; s; s &= s - 1) {
-                    const int32_t *p;
-                    int32_t rn, n;
-                    row(__builtin_ctz(s), l, &p, &rn);
-                    restrict_range(p, rn, lo, hi, &n);
+                int k = 0;
+                for (uint32_t s = N.t_diff; s; s &= s - 1, k++) {
+                    RowRef r = row(__builtin_ctz(s), l);
+                    int32_t n;
+                    int32_t b = restrict_row(r, lo, hi, &n);
                     cost += n;
+                    if (k == 0) {
+                        sp0 = r.p + b;
+                        sl0 = n;
+                        so0 = r.owner;
+                    } else if (k == 1) {
+                        sp1 = r.p + b;
+                        sl1 = n;
+                        so1 = r.owner;
+                    } else {
+                        sp2 = r.p + b;
+                        sl2 = n;
+                        so2 = r.owner;
+                    }
                 }
                 complement = cost < dlen;
             }
-            if ((P.run_flags & PG_RUN_COUNT_BYTES)) {
+            if (P.run_flags & PG_RUN_COUNT_BYTES) {
                 for (uint32_t s = N.t_diff; s; s &= s - 1) {
-                    const int32_t *p;
-                    int32_t rn, n;
-                    row(__builtin_ctz(s), l, &p, &rn);
-                    restrict_range(p, rn, lo, hi, &n);
+                    int32_t n;
+                    restrict_row(row(__builtin_ctz(s), l), lo, hi, &n);
                     bytes += n;
                 }
                 atomicAdd(&L.bytes, 4ull * (unsigned long long)bytes);
             }
             L.pcnt[l] = 0;
+            L.pdrv[l] = drv;
+            L.p1ptr[l] = dptr;
+            L.p1len[l] = dlen;
+            L.p1own[l] = downer;
             if (!complement) {
                 L.pmode[l] = 0;
-                L.pdrv[l] = drv;
-                L.p1ptr[l] = dptr;
-                L.p1len[l] = dlen;
                 L.pconst[l] = 0;
+                sp0 = dptr;
+                sl0 = dlen;
+                so0 = downer;
+                my_nseg = dlen > 0 ? 1 : 0;
+                my_tot = dlen;
             } else {
-                // the single positive operand P1 (restricted) is the driver
-                // found above; excluded images inside P1 \ (D...) are removed
+                // excluded images inside P1 \ (D...) were counted in |P1|
                 L.pmode[l] = 1;
-                L.pdrv[l] = drv;
-                L.p1ptr[l] = dptr;
-                L.p1len[l] = dlen;
                 int32_t c = dlen;
                 for (uint32_t s = N.excl; s; s &= s - 1) {
                     int32_t v = val(__builtin_ctz(s), l);
                     if (v <= lo || v >= hi) continue;
                     if (!contains(dptr, dlen, v)) continue;
                     bool in_d = false;
-                    for (uint32_t t = N.t_diff; t && !in_d; t &= t - 1) {
-                        const int32_t *p;
-                        int32_t rn;
-                        row(__builtin_ctz(t), l, &p, &rn);
-                        in_d = contains(p, rn, v);
-                    }
+                    for (uint32_t t = N.t_diff; t && !in_d; t &= t - 1) in_d = in_row(P, row(__builtin_ctz(t), l), v);
                     if (!in_d) c--;
                 }
                 L.pconst[l] = c;
-            }
-        }
-        wsync();
-        // segments, laid out by lane 0 (at most kSeg)
-        if (lane == 0) {
-            int ns = 0;
-            int32_t total = 0;
-            for (int l = 0; l < np; l++) {
-                if (L.pmode[l] < 0) continue;
-                if (L.pmode[l] == 0) {
-                    if (L.p1len[l] > 0) {
-                        L.seg_start[ns] = total;
-                        L.seg_prefix[ns] = (int16_t)l;
-                        L.seg_op[ns] = -1;
-                        L.seg_ptr[ns] = L.p1ptr[l];
-                        total += L.p1len[l];
-                        ns++;
-                    }
-                } else {
-                    int k = 0;
-                    for (uint32_t s = N.t_diff; s; s &= s - 1, k++) {
-                        const int32_t *p;
-                        int32_t rn, n;
-                        row(__builtin_ctz(s), l, &p, &rn);
-                        int32_t b = restrict_range(p, rn, L.plo[l], L.phi[l], &n);
-                        if (n > 0) {
-                            L.seg_start[ns] = total;
-                            L.seg_prefix[ns] = (int16_t)l;
-                            L.seg_op[ns] = (int16_t)k;
-                            L.seg_ptr[ns] = p + b;
-                            total += n;
-                            ns++;
-                        }
-                    }
+                // pack the non-empty difference segments, keeping their order
+                int k = 0;
+                const int32_t *q0 = nullptr, *q1 = nullptr, *q2 = nullptr;
+                int32_t m0 = 0, m1 = 0, m2 = 0;
+                int o0 = -1, o1 = -1, o2 = -1;
+                if (sl0 > 0) {
+                    q0 = sp0;
+                    m0 = sl0;
+                    o0 = so0;
+                    k++;
                 }
+                if (ndiff > 1 && sl1 > 0) {
+                    if (k == 0) {
+                        q0 = sp1;
+                        m0 = sl1;
+                        o0 = so1;
+                    } else {
+                        q1 = sp1;
+                        m1 = sl1;
+                        o1 = so1;
+                    }
+                    k++;
+                }
+                if (ndiff > 2 && sl2 > 0) {
+                    if (k == 0) {
+                        q0 = sp2;
+                        m0 = sl2;
+                        o0 = so2;
+                    } else if (k == 1) {
+                        q1 = sp2;
+                        m1 = sl2;
+                        o1 = so2;
+                    } else {
+                        q2 = sp2;
+                        m2 = sl2;
+                        o2 = so2;
+                    }
+                    k++;
+                }
+                sp0 = q0;
+                sl0 = m0;
+                so0 = o0;
+                sp1 = q1;
+                sl1 = m1;
+                so1 = o1;
+                sp2 = q2;
+                sl2 = m2;
+                so2 = o2;
+                my_nseg = k;
+                my_tot = m0 + m1 + m2;
             }
-            L.seg_start[ns] = total;
-            L.nseg = ns;
-            L.total = total;
         }
+        // lay the segments end to end with wave scans (no serial pass)
+        int nseg = 0, total = 0;
+        const int sbase = wave_scan_excl(my_nseg, lane, &nseg);
+        int obase = wave_scan_excl(my_tot, lane, &total);
+        if (my_nseg > 0) {
+            L.seg_start[sbase] = obase;
+            L.seg_prefix[sbase] = (int16_t)lane;
+            L.seg_own[sbase] = so0;
+            L.seg_ptr[sbase] = sp0;
+            obase += sl0;
+        }
+        if (my_nseg > 1) {
+            L.seg_start[sbase + 1] = obase;
+            L.seg_prefix[sbase + 1] = (int16_t)lane;
+            L.seg_own[sbase + 1] = so1;
+            L.seg_ptr[sbase + 1] = sp1;
+            obase += sl1;
+        }
+        if (my_nseg > 2) {
+            L.seg_start[sbase + 2] = obase;
+            L.seg_prefix[sbase + 2] = (int16_t)lane;
+            L.seg_own[sbase + 2] = so2;
+            L.seg_ptr[sbase + 2] = sp2;
+        }
+        if (lane == 0) L.seg_start[nseg] = total;
         wsync();
-        const int nseg = L.nseg;
-        const int32_t total = L.total;
+        int s = 0;  // this lane's segment, advanced monotonically
         for (int32_t tb = 0; tb < total; tb += 64) {
-            int32_t t = tb + lane;
+            const int32_t t = tb + lane;
             bool ok = false;
             int l = 0;
             int32_t e = 0;
             if (t < total) {
-                // segment holding flat index t
-                int s_lo = 0, s_n = nseg;
-                while (s_n > 1) {
-                    int half = s_n >> 1;
-                    if (L.seg_start[s_lo + half] <= t) {
-                        s_lo += half;
-                        s_n -= half;
-                    } else {
-                        s_n = half;
+                if (tb == 0) {
+                    // first visit: binary search for the segment holding t
+                    int s_lo = 0, s_n = nseg;
+                    while (s_n > 1) {
+                        const int half = s_n >> 1;
+                        if (L.seg_start[s_lo + half] <= t) {
+                            s_lo += half;
+                            s_n -= half;
+                        } else {
+                            s_n = half;
+                        }
                     }
+                    s = s_lo;
+                } else {
+                    while (L.seg_start[s + 1] <= t) s++;
                 }
-                const int s = s_lo;
                 l = L.seg_prefix[s];
                 e = L.seg_ptr[s][t - L.seg_start[s]];
                 if (L.pmode[l] == 0) {
                     ok = test_direct(N, x, l, L.pdrv[l], e, L.bptr[l], L.blen[l]);
                 } else {
-                    // complement term k: e in D_k, count it if e in P1 and in no earlier D
-                    const int k = L.seg_op[s];
-                    ok = contains(L.p1ptr[l], L.p1len[l], e);
-                    int kk = 0;
-                    for (uint32_t d = N.t_diff; d && ok && kk < k; d &= d - 1, kk++) {
-                        const int32_t *p;
-                        int32_t rn;
-                        row(__builtin_ctz(d), l, &p, &rn);
-                        ok = !contains(p, rn, e);
-                    }
+                    // complement term: e in D_k counts if e in P1 and in no
+                    // earlier D of this prefix (the segments just before)
+                    ok = in_range(P, L.p1ptr[l], L.p1len[l], L.p1own[l], e);
+                    for (int s2 = s - 1; ok && s2 >= 0 && L.seg_prefix[s2] == l; s2--)
+                        ok = !in_range(P, L.seg_ptr[s2], L.seg_start[s2 + 1] - L.seg_start[s2], L.seg_own[s2], e);
                 }
             }
             if (emit) {
-                unsigned long long bal = __ballot(ok);
+                const unsigned long long bal = __ballot(ok);
                 unsigned long long base = 0;
                 if (lane == 0 && bal) base = atomicAdd(P.emit_ctr, (unsigned long long)__popcll(bal));
                 base = __shfl(base, 0);
                 if (ok) {
-                    unsigned long long slot = base + (unsigned long long)__popcll(bal & ((1ull << lane) - 1ull));
+                    const unsigned long long slot = base + (unsigned long long)__popcll(bal & ((1ull << lane) - 1ull));
                     if (slot < P.cap) {
                         int32_t *o = P.out + slot * (unsigned long long)N.k;
                         for (int y = 0; y < x; y++) o[N.pv[y]] = P.perm[val(y, l)];
@@ -500,25 +571,24 @@ struct Ctx {
             unsigned long long contrib = 0;
             bool ovf = false;
             if (lane < np && L.pmode[lane] >= 0) {
-                unsigned long long c = L.pmode[lane] == 0 ? (unsigned long long)L.pcnt[lane]
-                                                          : (unsigned long long)(L.pconst[lane] - (int32_t)L.pcnt[lane]);
+                const unsigned long long c = L.pmode[lane] == 0
+                                                 ? (unsigned long long)L.pcnt[lane]
+                                                 : (unsigned long long)(L.pconst[lane] - (int32_t)L.pcnt[lane]);
                 contrib = choose(c, N.group, &ovf);
                 unsigned long long q;
                 if (__builtin_mul_overflow(contrib, N.mult, &q)) ovf = true;
                 contrib = q;
             }
             for (int off = 32; off > 0; off >>= 1) {
-                unsigned long long o = __shfl_xor(contrib, off);
-                unsigned long long s = contrib + o;
+                const unsigned long long o = __shfl_xor(contrib, off);
+                const unsigned long long s = contrib + o;
                 if (s < contrib) ovf = true;
                 contrib = s;
             }
-            if (__ballot(ovf)) {
-                if (lane == 0) atomicOr(P.flags, 1);
-            }
+            if (__ballot(ovf) && lane == 0) atomicOr(P.flags, 1);
             if (lane == 0) {
-                unsigned long long a = L.acc[N.plan];
-                unsigned long long s = a + contrib;
+                const unsigned long long a = L.acc[N.plan];
+                const unsigned long long s = a + contrib;
                 if (s < a) atomicOr(P.flags, 1);
                 L.acc[N.plan] = s;
                 if (P.mode == kModeExists && s > 0) {
@@ -530,7 +600,7 @@ struct Ctx {
         wsync();
     }
 
-    // run every count / emit child of node id `nid` over the candidates of
+    // run every count / emit child of node `nid` over the candidates of
     // level x held in setbuf(x) (length len), in batches of 64 prefixes
     __device__ void counts_over_set(int nid, int x, int32_t len) {
         const Node &N = P.nodes[nid];
@@ -546,29 +616,33 @@ struct Ctx {
         vl0 = x;
         vl1 = -1;
         for (int32_t s = 0; s < len; s += kP) {
-            int np = min(kP, len - s);
+            const int np = min(kP, len - s);
             if (lane < np) {
-                int32_t v = S[s + lane];
+                const int32_t v = S[s + lane];
+                const long long o = P.rp[v];
                 L.pv0[lane] = v;
-                L.po0[lane] = P.rp[v];
-                L.pl0[lane] = (int32_t)(P.rp[v + 1] - P.rp[v]);
-                L.pmode[lane] = 0;
+                L.po0[lane] = o;
+                L.pl0[lane] = (int32_t)(P.rp[v + 1] - o);
+                L.pu0[lane] = P.up[v];
+                L.pidx[lane] = s + lane;
             }
-            wsync();
             for (int c = 0; c < first_enum; c++) {
                 if (lane < np) L.pmode[lane] = 0;
                 wsync();
-                count_batch(P.nodes[cb + c], np);
+                count_batch(P.nodes[cb + c], np, x);
             }
         }
         vl0 = -1;
     }
 
-    __device__ void set_level(int x, int32_t v) {
+    __device__ __forceinline__ void set_level(int x, int32_t v, int32_t idx) {
         if (lane == 0) {
+            const long long o = P.rp[v];
             L.m[x] = v;
-            L.roff[x] = P.rp[v];
-            L.rlen[x] = (int32_t)(P.rp[v + 1] - P.rp[v]);
+            L.roff[x] = o;
+            L.rlen[x] = (int32_t)(P.rp[v + 1] - o);
+            L.rup[x] = P.up[v];
+            L.cur_idx[x] = idx;
         }
         wsync();
     }
@@ -583,6 +657,12 @@ struct Ctx {
         return L.stop != 0;
     }
 
+    __device__ __forceinline__ bool has_enum_child(const Node &N) const {
+        for (int c = 0; c < N.child_count; c++)
+            if (P.nodes[N.child_begin + c].kind == kEnum) return true;
+        return false;
+    }
+
     // depth-first walk of the enumeration children of root node rid, with
     // levels 0..1 already assigned in m[]
     __device__ void dfs(int rid) {
@@ -592,24 +672,20 @@ struct Ctx {
             const int e0 = cb + c;
             if (P.nodes[e0].kind != kEnum) continue;
             if (stopped()) return;
-            int32_t len = materialise(P.nodes[e0]);
+            const int32_t len = materialise(P.nodes[e0]);
             if (lane == 0) L.set_len[2] = len;
             wsync();
             if (len == 0) continue;
             counts_over_set(e0, 2, len);
+            if (!has_enum_child(P.nodes[e0])) continue;
             // stack of enumeration frames
-            int sp = 0;
-            auto push = [&](int nid, int x) {
-                if (lane == 0) {
-                    L.st_node[sp] = nid;
-                    L.st_idx[sp] = 0;
-                    L.st_child[sp] = 0;
-                }
-                sp++;
-                wsync();
-                (void)x;
-            };
-            push(e0, 2);
+            if (lane == 0) {
+                L.st_node[0] = e0;
+                L.st_idx[0] = 0;
+                L.st_child[0] = 0;
+            }
+            int sp = 1;
+            wsync();
             while (sp > 0) {
                 if (stopped()) return;
                 const int f = sp - 1;
@@ -618,41 +694,96 @@ struct Ctx {
                 const int x = N.level;
                 const int ncb = uni(N.child_begin), ncc = uni(N.child_count);
                 int ch = uni(L.st_child[f]);
-                int idx = uni(L.st_idx[f]);
+                const int idx = uni(L.st_idx[f]);
                 // advance to the next enumeration child
                 while (ch < ncc && P.nodes[ncb + ch].kind != kEnum) ch++;
                 if (ch >= ncc) {
-                    idx++;
-                    if (idx >= L.set_len[x]) {
+                    if (idx + 1 >= L.set_len[x]) {
                         sp--;
                         wsync();
                         continue;
                     }
                     if (lane == 0) {
-                        L.st_idx[f] = idx;
+                        L.st_idx[f] = idx + 1;
                         L.st_child[f] = 0;
                     }
                     wsync();
                     continue;
                 }
                 if (lane == 0) L.st_child[f] = ch + 1;
-                wsync();
-                set_level(x, setbuf(x)[idx]);
+                set_level(x, setbuf(x)[idx], idx);
                 const int nid2 = ncb + ch;
-                int32_t len2 = materialise(P.nodes[nid2]);
+                const int32_t len2 = materialise(P.nodes[nid2]);
                 if (lane == 0) L.set_len[x + 1] = len2;
                 wsync();
                 if (len2 == 0) continue;
                 counts_over_set(nid2, x + 1, len2);
-                bool has_enum = false;
-                const Node &N2 = P.nodes[nid2];
-                for (int c2 = 0; c2 < N2.child_count; c2++)
-                    if (P.nodes[N2.child_begin + c2].kind == kEnum) has_enum = true;
-                if (has_enum) push(nid2, x + 1);
+                if (has_enum_child(P.nodes[nid2])) {
+                    if (lane == 0) {
+                        L.st_node[sp] = nid2;
+                        L.st_idx[sp] = 0;
+                        L.st_child[sp] = 0;
+                    }
+                    sp++;
+                    wsync();
+                }
             }
         }
     }
 };
+
+// Anti-vertex check for candidate e at level x under prefix l (l < 0: the
+// fixed assignment only): the sets N(m(a)) \ m(xmask[a]) over the
+// anti-vertex's neighbour levels a must have an empty intersection.  Kept
+// out of line: rare, and large enough to crowd the hot loops' registers.
+__device__ __noinline__ bool av_check(const KParams &P, const Lds &L, int vl0, int vl1, const AVCheck &c, int x,
+                                      int l, int32_t e) {
+    auto val = [&](int y) -> int32_t {
+        if (y == x) return e;
+        if (l < 0) return L.m[y];
+        if (y == vl0) return L.pv0[l];
+        if (y == vl1) return L.pv1[l];
+        return L.m[y];
+    };
+    const int32_t *best = nullptr;
+    int32_t best_n = INT_MAX;
+    int best_a = -1;
+    for (int a = 0; a < kMaxLevels; a++) {
+        if (!(c.nbr >> a & 1u)) continue;
+        const int32_t v = val(a);
+        const int32_t n = (int32_t)(P.rp[v + 1] - P.rp[v]);
+        if (n < best_n) {
+            best_n = n;
+            best = P.col + P.rp[v];
+            best_a = a;
+        }
+    }
+    for (int32_t i = 0; i < best_n; i++) {
+        const int32_t w = best[i];
+        if (c.label >= 0 && (P.lab == nullptr || P.lab[w] != c.label)) continue;
+        bool in_all = true;
+        for (int a = 0; a < kMaxLevels && in_all; a++) {
+            if (!(c.nbr >> a & 1u)) continue;
+            // w must not be the image of a true pattern neighbour of a
+            for (uint32_t xm = c.xmask[a]; xm && in_all; xm &= xm - 1)
+                if (val(__builtin_ctz(xm)) == w) in_all = false;
+            if (!in_all || a == best_a) continue;
+            const int32_t v = val(a);
+            RowRef r;
+            r.p = P.col + P.rp[v];
+            r.n = (int32_t)(P.rp[v + 1] - P.rp[v]);
+            r.up = P.up[v];
+            r.owner = v;
+            if (!in_row(P, r, w)) in_all = false;
+        }
+        if (in_all) return false;
+    }
+    return true;
+}
+
+__device__ bool Ctx::av_pass(const AVCheck &c, int x, int l, int32_t e) const {
+    return av_check(P, L, vl0, vl1, c, x, l, e);
+}
 
 // Root checks (labels and anti-vertex checks on levels 0 / 1) for prefix l.
 __device__ bool root_ok(Ctx &C, const Node &R, int l) {
@@ -663,7 +794,7 @@ __device__ bool root_ok(Ctx &C, const Node &R, int l) {
     for (int i = 0; i < R.av_count; i++) {
         const AVCheck &c = P.avs[R.av_begin + i];
         // the deepest root level is the "candidate" of the check
-        int x = R.level;
+        const int x = R.level;
         if (!C.av_pass(c, x, l, C.val(x, l))) return false;
     }
     return true;
@@ -683,11 +814,20 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
     const long long total_tasks = P.n_etasks + P.n_vtasks;
     for (;;) {
         if (C.stopped()) break;
+        // guided claiming: tasks are sorted costliest first, so the chunk
+        // grows linearly from 1 at the head to P.chunk at the tail (the
+        // chunk is sized from a possibly stale cursor; any size is correct)
         unsigned long long t0 = 0;
-        if (lane == 0) t0 = atomicAdd(P.cursor, (unsigned long long)P.chunk);
+        long long chunk = 1;
+        if (lane == 0) {
+            const long long pos = (long long)__atomic_load_n(P.cursor, __ATOMIC_RELAXED);
+            chunk = 1 + (total_tasks > 0 ? (min(pos, total_tasks) * (long long)(P.chunk - 1)) / total_tasks : 0);
+            t0 = atomicAdd(P.cursor, (unsigned long long)chunk);
+        }
         t0 = __shfl(t0, 0);
+        chunk = __shfl(chunk, 0);
         if ((long long)t0 >= total_tasks) break;
-        const long long c_end = min((long long)t0 + P.chunk, total_tasks);
+        const long long c_end = min((long long)t0 + chunk, total_tasks);
         for (long long tb = (long long)t0; tb < c_end;) {
             // edge tasks occupy [0, n_etasks), vertex tasks the rest; a chunk
             // may straddle the boundary
@@ -700,7 +840,7 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
                 if ((R.kind == kRootEdge) != edge_phase) continue;
                 // load the prefix batch: tasks tb .. tb + np
                 if (lane < np) {
-                    long long t = tb + lane;
+                    const long long t = tb + lane;
                     int32_t u, v = 0;
                     if (edge_phase) {
                         u = P.tsrc[t];
@@ -710,13 +850,17 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
                     }
                     L.tu[lane] = u;
                     L.tv[lane] = v;
+                    const long long ou = P.rp[u];
                     L.pv0[lane] = u;
-                    L.po0[lane] = P.rp[u];
-                    L.pl0[lane] = (int32_t)(P.rp[u + 1] - P.rp[u]);
+                    L.po0[lane] = ou;
+                    L.pl0[lane] = (int32_t)(P.rp[u + 1] - ou);
+                    L.pu0[lane] = P.up[u];
                     L.pv1[lane] = v;
                     if (edge_phase) {
-                        L.po1[lane] = P.rp[v];
-                        L.pl1[lane] = (int32_t)(P.rp[v + 1] - P.rp[v]);
+                        const long long ov = P.rp[v];
+                        L.po1[lane] = ov;
+                        L.pl1[lane] = (int32_t)(P.rp[v + 1] - ov);
+                        L.pu1[lane] = P.up[v];
                     }
                 }
                 wsync();
@@ -726,26 +870,27 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
                 if (lane < np) okr = root_ok(C, R, lane);
                 const unsigned long long okmask = __ballot(okr);
                 const int cb = uni(R.child_begin), cc = uni(R.child_count);
+                bool any_enum = false;
                 for (int c = 0; c < cc; c++) {
                     const Node &N = P.nodes[cb + c];
-                    if (N.kind == kEnum) break;
+                    if (N.kind == kEnum) {
+                        any_enum = true;
+                        break;
+                    }
                     if (lane < np) L.pmode[lane] = okr ? 0 : -1;
                     wsync();
-                    C.count_batch(N, np);
+                    C.count_batch(N, np, -1);
                 }
                 C.vl0 = -1;
                 C.vl1 = -1;
                 // enumeration children: one task at a time
-                bool any_enum = false;
-                for (int c = 0; c < cc; c++)
-                    if (P.nodes[cb + c].kind == kEnum) any_enum = true;
                 if (!any_enum || !edge_phase) continue;
                 for (int l = 0; l < np; l++) {
                     if (!(okmask >> l & 1ull)) continue;
                     const int32_t u = L.tu[l], v = L.tv[l];
                     wsync();
-                    C.set_level(0, u);
-                    C.set_level(1, v);
+                    C.set_level(0, u, 0);
+                    C.set_level(1, v, 0);
                     C.dfs(rid);
                     if (C.stopped()) break;
                 }
@@ -756,10 +901,16 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
     }
     wsync();
     if (lane < P.n_plans && L.acc[lane]) {
-        unsigned long long old = atomicAdd(P.counts + lane, L.acc[lane]);
+        const unsigned long long old = atomicAdd(P.counts + lane, L.acc[lane]);
         if (old + L.acc[lane] < old) atomicOr(P.flags, 1);
     }
     if (lane == 0 && L.bytes) atomicAdd(P.bytes_ctr, L.bytes);
+}
+
+int match_blocks_per_cu() {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, match_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
+    return nb;
 }
 
 hipError_t launch_match(const KParams &P, int grid, hipStream_t s) {

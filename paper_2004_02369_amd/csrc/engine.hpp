@@ -12,6 +12,10 @@ enum RunMode : int32_t { kModeCount = 0, kModeExists = 1, kModeEmit = 2 };
 struct KParams {
     const int64_t *rp;
     const int32_t *col;
+    const int32_t *up;         // per vertex: index in its row of the first neighbour above it
+    const uint32_t *hub_bits;  // dense adjacency bitmaps of vertices hub_start..n-1 (hub_words each)
+    long long hub_words;
+    int32_t hub_start;
     const int16_t *lab;
     const int32_t *perm;
     const int32_t *tsrc;
@@ -40,5 +44,8 @@ struct KParams {
 };
 
 hipError_t launch_match(const KParams &P, int grid, hipStream_t s);
+
+// resident wavefronts (one per workgroup) per compute unit for match_kernel
+int match_blocks_per_cu();
 
 }  // namespace pg

@@ -218,6 +218,8 @@ void close_order(uint32_t lt[kMaxK], int k) {
 // Grochow-Kellis: while the (pointwise stabiliser) group is not trivial,
 // take the largest orbit, order its smallest vertex below every other
 // member, and fix that vertex.  |Aut_t| is the product of the orbit sizes.
+// (Any choice breaks the symmetry exactly; this one reproduces the paper's
+// diamond example.)
 SymmetryBreak break_symmetries(const Typed &t) {
     SymmetryBreak sb;
     AutSearch S(t);
@@ -639,8 +641,8 @@ pg_status compile_plan(const pg_pattern_desc *desc, const pg_plan_options *opt, 
     int mode = opt ? opt->mode : PG_PLAN_AUTO;
     if (mode < PG_PLAN_AUTO || mode > PG_PLAN_PARTIAL_ORDER) { *err = "unknown plan mode"; return PG_EINVAL; }
 
-    SymmetryBreak sb = break_symmetries(t);
     uint32_t core = min_connected_cover(t);
+    SymmetryBreak sb = break_symmetries(t);
 
     std::vector<std::vector<int>> les;
     std::vector<int> seq;
