@@ -170,7 +170,7 @@ typedef struct {
 
 #define PG_RUN_COUNT_BYTES 1  /* also count the merge-model bytes of every set operation */
 #define PG_RUN_NO_MODE_B 2    /* never count by complement (|A| - |A & B|) */
-#define PG_RUN_ROOT_VERTEX 4  /* reserved */
+#define PG_RUN_NO_TASK_BATCH 4  /* expand level 2 one root task at a time only */
 
 typedef struct {
     double kernel_ms;        /* device time of the matching kernel (HIP events) */

@@ -52,7 +52,7 @@ struct pg_graph {
     int32_t d_max = 0;
     int32_t device = 0;
     int32_t n_cu = 0;
-    int32_t blocks_per_cu = 0;  // resident match_kernel wavefronts per CU
+    int32_t blocks_per_cu[2] = {0, 0};  // resident match_kernel wavefronts per CU (without / with anti-vertices)
     bool labelled = false;
     std::vector<int32_t> perm;  // rank -> original id
     // device arrays
@@ -98,6 +98,7 @@ struct pg_graph {
 namespace {
 
 constexpr int64_t kHubMinDegree = 128;
+constexpr long long kArenaInts = 16384;  // per wavefront
 constexpr int64_t kHubBudgetBytes = int64_t(1) << 30;
 
 constexpr int kCtlCounts = 0;
@@ -272,7 +273,8 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         hipDeviceProp_t prop;
         PG_HIP(hipGetDeviceProperties(&prop, dev));
         g->n_cu = prop.multiProcessorCount;
-        g->blocks_per_cu = pg::match_blocks_per_cu();
+        g->blocks_per_cu[0] = pg::match_blocks_per_cu(false);
+        g->blocks_per_cu[1] = pg::match_blocks_per_cu(true);
         pg_status st;
         if ((st = upload(&g->rp, rp, &g->device_bytes))) return st;
         if ((st = upload(&g->col, col, &g->device_bytes))) return st;
@@ -467,14 +469,17 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
 
     // launch shape
     // persistent grid: exactly the wavefronts that can be resident at once
-    int grid = cfg && cfg->grid_waves ? cfg->grid_waves : g->n_cu * g->blocks_per_cu;
+    const bool with_av = !T.avs.empty();
+    int grid = cfg && cfg->grid_waves ? cfg->grid_waves : g->n_cu * g->blocks_per_cu[with_av ? 1 : 0];
     const long long n_et = T.has_edge_root ? (long long)g->m : 0;
     const long long n_vt = T.has_vertex_root ? (long long)g->n : 0;
     int chunk = cfg && cfg->chunk ? cfg->chunk : 64;
     // scratch: one set per enumeration level (levels 2 .. max_level-2)
     const int enum_levels = std::max(0, T.max_level - 3);
     const long long set_cap = std::max<long long>(1, g->d_max);
-    const size_t need_ints = (size_t)grid * (size_t)enum_levels * (size_t)set_cap;
+    // level-2 arena for task batches (candidates of up to 64 edge tasks)
+    const long long arena_cap = enum_levels ? kArenaInts : 0;
+    const size_t need_ints = (size_t)grid * ((size_t)enum_levels * (size_t)set_cap + (size_t)arena_cap);
     if (need_ints > g->scratch_ints) {
         dfree(g->scratch);
         g->scratch = nullptr;
@@ -509,8 +514,9 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     P.out = la.out;
     P.bytes_ctr = g->ctl + kCtlBytes;
     P.scratch = enum_levels ? g->scratch : nullptr;
-    P.wave_stride = (long long)enum_levels * set_cap;
+    P.wave_stride = (long long)enum_levels * set_cap + arena_cap;
     P.set_cap = set_cap;
+    P.arena_cap = arena_cap;
     P.n_etasks = n_et;
     P.n_vtasks = n_vt;
     P.cap = la.cap;
@@ -525,7 +531,7 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     PG_HIP(hipEventCreate(&e0));
     PG_HIP(hipEventCreate(&e1));
     PG_HIP(hipEventRecord(e0, s));
-    hipError_t le = pg::launch_match(P, grid, s);
+    hipError_t le = pg::launch_match(P, grid, with_av, s);
     if (le != hipSuccess) {
         edestroy(e0);
         edestroy(e1);

@@ -51,8 +51,16 @@ struct Lds {
     int32_t st_node[kMaxLevels];
     int32_t st_idx[kMaxLevels];
     int32_t st_child[kMaxLevels];
-    // root tasks of the current batch
+    // root tasks of the current batch and their rows (levels 0 and 1)
     int32_t tu[kP], tv[kP];
+    long long tro0[kP], tro1[kP];
+    int32_t trl0[kP], trl1[kP], tru0[kP], tru1[kP];
+    // level-2 candidates of a whole task batch, in the arena: task t owns
+    // [tstart[t], tstart[t] + tcnt[t]); prefixes of a task batch record their task
+    int32_t tstart[kP + 1];
+    int32_t tcnt[kP];
+    int32_t tbig[kP];
+    int32_t ptask[kP];
     // prefix batch: values and rows of the (at most two) varying levels
     int32_t pv0[kP], pv1[kP];
     long long po0[kP], po1[kP];
@@ -175,19 +183,29 @@ __device__ __forceinline__ bool in_range(const KParams &P, const int32_t *p, int
     return contains(p, n, e);
 }
 
+template <bool kAV>
 struct Ctx {
-    const KParams &P;
+    const KParams P;  // by value: a reference to the kernel argument would force a private copy
     Lds &L;
     int32_t *buf0;  // this wave's scratch (level 2 at offset 0)
     int lane;
     int vl0, vl1;   // varying levels of the current prefix batch (-1 none)
+    int tmode;      // 1: prefixes are (task, level-2 candidate) pairs of a task batch
+    int32_t *arena; // this wave's level-2 arena for task batches
 
-    __device__ Ctx(const KParams &p, Lds &l, int32_t *b, int ln) : P(p), L(l), buf0(b), lane(ln), vl0(-1), vl1(-1) {}
+    __device__ Ctx(const KParams &p, Lds &l, int32_t *b, int ln)
+        : P(p), L(l), buf0(b), lane(ln), vl0(-1), vl1(-1), tmode(0), arena(nullptr) {}
 
     __device__ __forceinline__ int32_t *setbuf(int level) const { return buf0 + (long long)(level - 2) * P.set_cap; }
 
     __device__ __forceinline__ int32_t val(int y, int l) const {
         if (l < 0) return L.m[y];
+        if (tmode) {
+            if (y == 2) return L.pv0[l];
+            if (y == 0) return L.tu[L.ptask[l]];
+            if (y == 1) return L.tv[L.ptask[l]];
+            return L.m[y];
+        }
         if (y == vl0) return L.pv0[l];
         if (y == vl1) return L.pv1[l];
         return L.m[y];
@@ -195,7 +213,18 @@ struct Ctx {
 
     __device__ __forceinline__ RowRef row(int y, int l) const {
         RowRef r;
-        if (l >= 0 && y == vl0) {
+        if (l >= 0 && tmode && y < 2) {
+            const int t = L.ptask[l];
+            r.p = P.col + (y == 0 ? L.tro0[t] : L.tro1[t]);
+            r.n = y == 0 ? L.trl0[t] : L.trl1[t];
+            r.up = y == 0 ? L.tru0[t] : L.tru1[t];
+            r.owner = y == 0 ? L.tu[t] : L.tv[t];
+        } else if (l >= 0 && tmode && y == 2) {
+            r.p = P.col + L.po0[l];
+            r.n = L.pl0[l];
+            r.up = L.pu0[l];
+            r.owner = L.pv0[l];
+        } else if (l >= 0 && y == vl0) {
             r.p = P.col + L.po0[l];
             r.n = L.pl0[l];
             r.up = L.pu0[l];
@@ -240,14 +269,15 @@ struct Ctx {
         for (uint32_t td = N.t_diff; td && ok; td &= td - 1) ok = !in_row(P, row(__builtin_ctz(td), l), e);
         for (uint32_t ex = N.excl; ex && ok; ex &= ex - 1) ok = e != val(__builtin_ctz(ex), l);
         if (ok && N.label >= 0) ok = P.lab != nullptr && P.lab[e] == N.label;
-        for (int i = 0; i < N.av_count && ok; i++) ok = av_pass(P.avs[N.av_begin + i], x, l, e);
+        if constexpr (kAV)
+            for (int i = 0; i < N.av_count && ok; i++) ok = av_pass(P.avs[N.av_begin + i], x, l, e);
         return ok;
     }
 
     // ---------------------------------------------------------------
     // Materialise the candidate set of enumeration node N (level x) for the
     // fixed assignment m[0..x): returns its length, elements in setbuf(x).
-    __device__ int32_t materialise(const Node &N) {
+    __device__ __forceinline__ int32_t materialise(const Node &N) {
         const int x = N.level;
         int32_t lo = -1, hi = INT_MAX;
         for (uint32_t s = N.lo; s; s &= s - 1) lo = max(lo, L.m[__builtin_ctz(s)]);
@@ -320,7 +350,7 @@ struct Ctx {
     // prefixes already loaded into the batch arrays (pv*, po*, pl*, pu*,
     // pmode; pidx when own >= 0: the prefixes are the elements of level
     // own's set, so a base range bounded by the prefix itself is known).
-    __device__ void count_batch(const Node &N, int np, int own) {
+    __device__ __forceinline__ void count_batch(const Node &N, int np, int own) {
         const int x = N.level;
         const bool emit = N.kind == kEmit;
         int my_nseg = 0, my_tot = 0;
@@ -337,8 +367,10 @@ struct Ctx {
             int drv = -1, downer = -1;
             long long bytes = 0;
             if (N.base >= 0) {
-                const int32_t *B = setbuf(N.base);
-                const int32_t Bn = L.set_len[N.base];
+                // in a task batch the only materialised level is 2: the
+                // prefix's task slice of the arena
+                const int32_t *B = tmode ? arena + L.tstart[L.ptask[l]] : setbuf(N.base);
+                const int32_t Bn = tmode ? L.tcnt[L.ptask[l]] : L.set_len[N.base];
                 int32_t b, e;
                 if (lo >= hi - 1) {
                     b = e = 0;
@@ -346,6 +378,9 @@ struct Ctx {
                     const int32_t i = L.pidx[l], pv = L.pv0[l];
                     b = lo < 0 ? 0 : (lo == pv ? i + 1 : lower_bound(B, Bn, lo + 1));
                     e = hi == INT_MAX ? Bn : (hi == pv ? i : lower_bound(B, Bn, hi));
+                } else if (tmode) {
+                    b = lo < 0 ? 0 : lower_bound(B, Bn, lo + 1);
+                    e = hi == INT_MAX ? Bn : lower_bound(B, Bn, hi);
                 } else {
                     const int32_t cur = L.m[N.base], ci = L.cur_idx[N.base];
                     b = lo < 0 ? 0 : (lo == cur ? ci + 1 : lower_bound(B, Bn, lo + 1));
@@ -602,7 +637,7 @@ struct Ctx {
 
     // run every count / emit child of node `nid` over the candidates of
     // level x held in setbuf(x) (length len), in batches of 64 prefixes
-    __device__ void counts_over_set(int nid, int x, int32_t len) {
+    __device__ __forceinline__ void counts_over_set(int nid, int x, int32_t len) {
         const Node &N = P.nodes[nid];
         const int cb = uni(N.child_begin), cc = uni(N.child_count);
         int first_enum = cc;
@@ -647,7 +682,7 @@ struct Ctx {
         wsync();
     }
 
-    __device__ bool stopped() {
+    __device__ __forceinline__ bool stopped() {
         if (P.mode != kModeExists) return false;
         if (lane == 0) {
             int f = __atomic_load_n(P.flags + 1, __ATOMIC_RELAXED);
@@ -663,21 +698,186 @@ struct Ctx {
         return false;
     }
 
-    // depth-first walk of the enumeration children of root node rid, with
-    // levels 0..1 already assigned in m[]
-    __device__ void dfs(int rid) {
+    // Level-2 enumeration node E whose children are all count / emit nodes,
+    // for a whole batch of np edge tasks at once: one flattened pass
+    // materialises every task's candidates into the arena (in task order,
+    // each task's slice sorted), then the count children run flattened over
+    // all (task, candidate) prefixes.  Tasks whose driver does not fit the
+    // arena take the one-task path afterwards.
+    __device__ __forceinline__ void leaf_batch(int eid, int np, unsigned long long okmask) {
+        const Node &E = P.nodes[eid];
+        // the task rows as prefix rows (a previous batch's count phase
+        // reused the prefix arrays)
+        if (lane < np) {
+            L.pv0[lane] = L.tu[lane];
+            L.po0[lane] = L.tro0[lane];
+            L.pl0[lane] = L.trl0[lane];
+            L.pu0[lane] = L.tru0[lane];
+            L.pv1[lane] = L.tv[lane];
+            L.po1[lane] = L.tro1[lane];
+            L.pl1[lane] = L.trl1[lane];
+            L.pu1[lane] = L.tru1[lane];
+        }
+        wsync();
+        tmode = 0;
+        vl0 = 0;
+        vl1 = 1;
+        int32_t dlen = 0;
+        const int32_t *dptr = nullptr;
+        int drv = -1;
+        const bool ok = lane < np && (okmask >> lane & 1ull);
+        if (ok) {
+            int32_t lo = -1, hi = INT_MAX;
+            for (uint32_t s = E.lo; s; s &= s - 1) lo = max(lo, val(__builtin_ctz(s), lane));
+            for (uint32_t s = E.hi; s; s &= s - 1) hi = min(hi, val(__builtin_ctz(s), lane));
+            dlen = INT_MAX;
+            long long bytes = 0;
+            for (uint32_t s = E.t_isect; s; s &= s - 1) {
+                const int y = __builtin_ctz(s);
+                RowRef r = row(y, lane);
+                int32_t n;
+                const int32_t b = restrict_row(r, lo, hi, &n);
+                bytes += n;
+                if (n < dlen) {
+                    dlen = n;
+                    dptr = r.p + b;
+                    drv = y;
+                }
+            }
+            if (dlen == INT_MAX) dlen = 0;
+            if (P.run_flags & PG_RUN_COUNT_BYTES) {
+                for (uint32_t s = E.t_diff; s; s &= s - 1) {
+                    int32_t n;
+                    restrict_row(row(__builtin_ctz(s), lane), lo, hi, &n);
+                    bytes += n;
+                }
+                atomicAdd(&L.bytes, 4ull * (unsigned long long)bytes);
+            }
+        }
+        int tot = 0;
+        const int off = wave_scan_excl(dlen, lane, &tot);
+        const bool big = ok && (long long)off + dlen > P.arena_cap;
+        const int32_t flen = (ok && !big) ? dlen : 0;
+        int total = 0, nseg = 0;
+        const int obase = wave_scan_excl(flen, lane, &total);
+        const int sidx = wave_scan_excl(flen > 0 ? 1 : 0, lane, &nseg);
+        if (flen > 0) {
+            L.seg_start[sidx] = obase;
+            L.seg_prefix[sidx] = (int16_t)lane;
+            L.seg_ptr[sidx] = dptr;
+        }
+        if (lane < kP) {
+            L.pdrv[lane] = drv;
+            L.tcnt[lane] = 0;
+            L.tbig[lane] = big ? 1 : 0;
+        }
+        if (lane == 0) L.seg_start[nseg] = total;
+        wsync();
+        int32_t out_n = 0;
+        int s = 0;
+        for (int32_t tb = 0; tb < total; tb += 64) {
+            const int32_t t = tb + lane;
+            bool pass = false;
+            int l = 0;
+            int32_t e = 0;
+            if (t < total) {
+                if (tb == 0) {
+                    int s_lo = 0, s_n = nseg;
+                    while (s_n > 1) {
+                        const int half = s_n >> 1;
+                        if (L.seg_start[s_lo + half] <= t) {
+                            s_lo += half;
+                            s_n -= half;
+                        } else {
+                            s_n = half;
+                        }
+                    }
+                    s = s_lo;
+                } else {
+                    while (L.seg_start[s + 1] <= t) s++;
+                }
+                l = L.seg_prefix[s];
+                e = L.seg_ptr[s][t - L.seg_start[s]];
+                pass = test_direct(E, 2, l, L.pdrv[l], e, nullptr, 0);
+            }
+            const unsigned long long bal = __ballot(pass);
+            if (pass) {
+                arena[out_n + (int32_t)__popcll(bal & ((1ull << lane) - 1ull))] = e;
+                atomicAdd(&L.tcnt[l], 1);
+            }
+            out_n += (int32_t)__popcll(bal);
+        }
+        wsync();
+        // survivors are in task order: slices start at the scan of the counts
+        int ntot = 0;
+        const int32_t tc = lane < np ? L.tcnt[lane] : 0;
+        const int32_t st = wave_scan_excl(tc, lane, &ntot);
+        if (lane < np) L.tstart[lane] = st;
+        if (lane == 0) L.tstart[np] = ntot;
+        wsync();
+        vl0 = -1;
+        vl1 = -1;
+        tmode = 1;
+        const int cb = uni(E.child_begin), cc = uni(E.child_count);
+        for (int32_t s0 = 0; s0 < ntot; s0 += kP) {
+            const int np2 = min(kP, ntot - s0);
+            if (lane < np2) {
+                const int32_t idx = s0 + lane;
+                // task holding arena index idx: last t with tstart[t] <= idx
+                int t_lo = 0, t_n = np;
+                while (t_n > 1) {
+                    const int half = t_n >> 1;
+                    if (L.tstart[t_lo + half] <= idx) {
+                        t_lo += half;
+                        t_n -= half;
+                    } else {
+                        t_n = half;
+                    }
+                }
+                const int32_t v = arena[idx];
+                const long long o = P.rp[v];
+                L.ptask[lane] = t_lo;
+                L.pidx[lane] = idx - L.tstart[t_lo];
+                L.pv0[lane] = v;
+                L.po0[lane] = o;
+                L.pl0[lane] = (int32_t)(P.rp[v + 1] - o);
+                L.pu0[lane] = P.up[v];
+            }
+            for (int c = 0; c < cc; c++) {
+                if (lane < np2) L.pmode[lane] = 0;
+                wsync();
+                count_batch(P.nodes[cb + c], np2, 2);
+            }
+        }
+        tmode = 0;
+        // tasks too large for the arena: one at a time into setbuf(2)
+        for (int l = 0; l < np; l++) {
+            if (!L.tbig[l]) continue;
+            set_level(0, L.tu[l], 0);
+            set_level(1, L.tv[l], 0);
+            const int32_t len = materialise(E);
+            if (lane == 0) L.set_len[2] = len;
+            wsync();
+            if (len > 0) counts_over_set(eid, 2, len);
+        }
+    }
+
+    // depth-first walk of the enumeration children of root node rid that
+    // have enumeration children themselves (the others run as task batches),
+    // with levels 0..1 already assigned in m[]
+    __device__ __forceinline__ void dfs(int rid) {
         const Node &R = P.nodes[rid];
         const int cb = uni(R.child_begin), cc = uni(R.child_count);
         for (int c = 0; c < cc; c++) {
             const int e0 = cb + c;
             if (P.nodes[e0].kind != kEnum) continue;
+            if (!has_enum_child(P.nodes[e0]) && !(P.run_flags & PG_RUN_NO_TASK_BATCH)) continue;
             if (stopped()) return;
             const int32_t len = materialise(P.nodes[e0]);
             if (lane == 0) L.set_len[2] = len;
             wsync();
             if (len == 0) continue;
             counts_over_set(e0, 2, len);
-            if (!has_enum_child(P.nodes[e0])) continue;
             // stack of enumeration frames
             if (lane == 0) {
                 L.st_node[0] = e0;
@@ -732,25 +932,17 @@ struct Ctx {
     }
 };
 
-// Anti-vertex check for candidate e at level x under prefix l (l < 0: the
-// fixed assignment only): the sets N(m(a)) \ m(xmask[a]) over the
+// Anti-vertex check: vals[y] is the image of level y (the candidate
+// included).  The sets N(vals[a]) \ {vals[y] : y in xmask[a]} over the
 // anti-vertex's neighbour levels a must have an empty intersection.  Kept
 // out of line: rare, and large enough to crowd the hot loops' registers.
-__device__ __noinline__ bool av_check(const KParams &P, const Lds &L, int vl0, int vl1, const AVCheck &c, int x,
-                                      int l, int32_t e) {
-    auto val = [&](int y) -> int32_t {
-        if (y == x) return e;
-        if (l < 0) return L.m[y];
-        if (y == vl0) return L.pv0[l];
-        if (y == vl1) return L.pv1[l];
-        return L.m[y];
-    };
+__device__ __noinline__ bool av_check(const KParams &P, const int32_t *vals, const AVCheck &c) {
     const int32_t *best = nullptr;
     int32_t best_n = INT_MAX;
     int best_a = -1;
     for (int a = 0; a < kMaxLevels; a++) {
         if (!(c.nbr >> a & 1u)) continue;
-        const int32_t v = val(a);
+        const int32_t v = vals[a];
         const int32_t n = (int32_t)(P.rp[v + 1] - P.rp[v]);
         if (n < best_n) {
             best_n = n;
@@ -766,9 +958,9 @@ __device__ __noinline__ bool av_check(const KParams &P, const Lds &L, int vl0, i
             if (!(c.nbr >> a & 1u)) continue;
             // w must not be the image of a true pattern neighbour of a
             for (uint32_t xm = c.xmask[a]; xm && in_all; xm &= xm - 1)
-                if (val(__builtin_ctz(xm)) == w) in_all = false;
+                if (vals[__builtin_ctz(xm)] == w) in_all = false;
             if (!in_all || a == best_a) continue;
-            const int32_t v = val(a);
+            const int32_t v = vals[a];
             RowRef r;
             r.p = P.col + P.rp[v];
             r.n = (int32_t)(P.rp[v + 1] - P.rp[v]);
@@ -781,31 +973,51 @@ __device__ __noinline__ bool av_check(const KParams &P, const Lds &L, int vl0, i
     return true;
 }
 
-__device__ bool Ctx::av_pass(const AVCheck &c, int x, int l, int32_t e) const {
-    return av_check(P, L, vl0, vl1, c, x, l, e);
+// every level value comes from Ctx::val, which knows the batch layout
+// (fixed assignment, root batch, set batch or task batch)
+template <bool kAV>
+__device__ bool Ctx<kAV>::av_pass(const AVCheck &c, int x, int l, int32_t e) const {
+    int32_t vals[kMaxLevels];
+    for (int y = 0; y < kMaxLevels; y++) vals[y] = y < x ? val(y, l) : (y == x ? e : 0);
+    return av_check(P, vals, c);
 }
 
 // Root checks (labels and anti-vertex checks on levels 0 / 1) for prefix l.
-__device__ bool root_ok(Ctx &C, const Node &R, int l) {
+template <bool kAV>
+__device__ __forceinline__ bool root_ok(Ctx<kAV> &C, const Node &R, int l) {
     const KParams &P = C.P;
     if (R.label0 >= 0 && (P.lab == nullptr || P.lab[C.L.pv0[l]] != R.label0)) return false;
     if (R.kind == kRootEdge && R.label1 >= 0 && (P.lab == nullptr || P.lab[C.L.pv1[l]] != R.label1))
         return false;
-    for (int i = 0; i < R.av_count; i++) {
-        const AVCheck &c = P.avs[R.av_begin + i];
-        // the deepest root level is the "candidate" of the check
-        const int x = R.level;
-        if (!C.av_pass(c, x, l, C.val(x, l))) return false;
-    }
+    if constexpr (kAV)
+        for (int i = 0; i < R.av_count; i++) {
+            const AVCheck &c = P.avs[R.av_begin + i];
+            // the deepest root level is the "candidate" of the check
+            const int x = R.level;
+            if (!C.av_pass(c, x, l, C.val(x, l))) return false;
+        }
     return true;
 }
 
+// kAV: the trie holds anti-vertex checks (the variant without them keeps
+// the out-of-line check and its call frame out of the hot loops)
+template <bool kAV>
 __global__ void __launch_bounds__(64) match_kernel(KParams P) {
     __shared__ Lds L;
     const int lane = threadIdx.x;
     int32_t *buf0 = P.scratch ? P.scratch + (long long)blockIdx.x * P.wave_stride : nullptr;
-    Ctx C(P, L, buf0, lane);
+    Ctx<kAV> C(P, L, buf0, lane);
+    C.arena = buf0 ? buf0 + P.wave_stride - P.arena_cap : nullptr;
     for (int i = lane; i < kMaxPlansPerLaunch; i += 64) L.acc[i] = 0;
+    if (lane < kMaxLevels) {
+        // a valid vertex in every slot of the fixed assignment
+        L.m[lane] = 0;
+        L.roff[lane] = 0;
+        L.rlen[lane] = 0;
+        L.rup[lane] = 0;
+        L.cur_idx[lane] = 0;
+        L.set_len[lane] = 0;
+    }
     if (lane == 0) {
         L.stop = 0;
         L.bytes = 0;
@@ -856,11 +1068,17 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
                     L.pl0[lane] = (int32_t)(P.rp[u + 1] - ou);
                     L.pu0[lane] = P.up[u];
                     L.pv1[lane] = v;
+                    L.tro0[lane] = ou;
+                    L.trl0[lane] = L.pl0[lane];
+                    L.tru0[lane] = L.pu0[lane];
                     if (edge_phase) {
                         const long long ov = P.rp[v];
                         L.po1[lane] = ov;
                         L.pl1[lane] = (int32_t)(P.rp[v + 1] - ov);
                         L.pu1[lane] = P.up[v];
+                        L.tro1[lane] = ov;
+                        L.trl1[lane] = L.pl1[lane];
+                        L.tru1[lane] = L.pu1[lane];
                     }
                 }
                 wsync();
@@ -883,8 +1101,21 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
                 }
                 C.vl0 = -1;
                 C.vl1 = -1;
-                // enumeration children: one task at a time
                 if (!any_enum || !edge_phase) continue;
+                // enumeration children with only count children: whole batch
+                bool any_deep = false;
+                for (int c = 0; c < cc; c++) {
+                    const int eid = cb + c;
+                    if (P.nodes[eid].kind != kEnum) continue;
+                    if (C.has_enum_child(P.nodes[eid]) || (P.run_flags & PG_RUN_NO_TASK_BATCH)) {
+                        any_deep = true;
+                        continue;
+                    }
+                    if (C.stopped()) break;
+                    C.leaf_batch(eid, np, okmask);
+                }
+                // deeper enumeration children: one task at a time
+                if (!any_deep) continue;
                 for (int l = 0; l < np; l++) {
                     if (!(okmask >> l & 1ull)) continue;
                     const int32_t u = L.tu[l], v = L.tv[l];
@@ -907,14 +1138,17 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
     if (lane == 0 && L.bytes) atomicAdd(P.bytes_ctr, L.bytes);
 }
 
-int match_blocks_per_cu() {
+int match_blocks_per_cu(bool with_av) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, match_kernel, 64, 0) != hipSuccess || nb < 1) nb = 8;
+    hipError_t e = with_av ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, match_kernel<true>, 64, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, match_kernel<false>, 64, 0);
+    if (e != hipSuccess || nb < 1) nb = 8;
     return nb;
 }
 
-hipError_t launch_match(const KParams &P, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(match_kernel, dim3(grid), dim3(64), 0, s, P);
+hipError_t launch_match(const KParams &P, int grid, bool with_av, hipStream_t s) {
+    if (with_av) hipLaunchKernelGGL(match_kernel<true>, dim3(grid), dim3(64), 0, s, P);
+    else hipLaunchKernelGGL(match_kernel<false>, dim3(grid), dim3(64), 0, s, P);
     return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ struct KParams {
     int32_t *scratch;
     long long wave_stride;     // ints per wave
     long long set_cap;         // ints per materialised level
+    long long arena_cap;       // ints of the level-2 arena at the end of each wave's scratch
     long long n_etasks;
     long long n_vtasks;
     unsigned long long cap;    // emit capacity (rows)
@@ -43,9 +44,10 @@ struct KParams {
     int32_t run_flags;
 };
 
-hipError_t launch_match(const KParams &P, int grid, hipStream_t s);
+// with_av: the trie holds anti-vertex checks (selects the kernel variant)
+hipError_t launch_match(const KParams &P, int grid, bool with_av, hipStream_t s);
 
 // resident wavefronts (one per workgroup) per compute unit for match_kernel
-int match_blocks_per_cu();
+int match_blocks_per_cu(bool with_av);
 
 }  // namespace pg

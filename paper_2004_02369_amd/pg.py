@@ -23,7 +23,7 @@ PG_OK, PG_STOPPED = 0, 1
 PG_EINVAL, PG_ENOMEM, PG_EDEVICE, PG_EOVERFLOW, PG_EUNSUPPORTED = -1, -2, -3, -4, -5
 PG_EDGE, PG_ANTI_EDGE = 0, 1
 PG_PLAN_AUTO, PG_PLAN_LINEAR_EXT, PG_PLAN_PARTIAL_ORDER = 0, 1, 2
-PG_RUN_COUNT_BYTES, PG_RUN_NO_MODE_B = 1, 2
+PG_RUN_COUNT_BYTES, PG_RUN_NO_MODE_B, PG_RUN_NO_TASK_BATCH = 1, 2, 4
 
 _STATUS = {PG_EINVAL: "EINVAL", PG_ENOMEM: "ENOMEM", PG_EDEVICE: "EDEVICE", PG_EOVERFLOW: "EOVERFLOW",
            PG_EUNSUPPORTED: "EUNSUPPORTED"}

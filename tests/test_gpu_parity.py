@@ -185,7 +185,8 @@ def test_batched_equals_single_and_perturbations(pg, orc):
     og = orc.Graph.from_tuple(g)
     assert batched == [orc.count(og, s) for s in specs]
     for grid, chunk, flags in [(1, 1, 0), (7, 3, 0), (64, 1000, 0), (300, 64, pg.PG_RUN_NO_MODE_B),
-                               (2048, 16, pg.PG_RUN_COUNT_BYTES)]:
+                               (2048, 16, pg.PG_RUN_COUNT_BYTES), (512, 64, pg.PG_RUN_NO_TASK_BATCH),
+                               (100, 8, pg.PG_RUN_NO_TASK_BATCH | pg.PG_RUN_NO_MODE_B)]:
         say("perturbation", grid, chunk, flags)
         assert pg.count(Gd, plans, grid_waves=grid, chunk=chunk, flags=flags) == batched
 
