@@ -36,7 +36,7 @@
 namespace pg {
 
 constexpr int kP = 64;        // prefixes per flattened batch (one per lane)
-constexpr int kMaxDiffB = 3;  // complement counting handles up to this many difference rows
+constexpr int kMaxDiffB = 2;  // complement counting handles up to this many difference rows
 constexpr int kSeg = kP * kMaxDiffB;
 constexpr int kBaseOp = 31;   // operand id of the base set
 
@@ -59,19 +59,16 @@ struct Lds {
     // [tstart[t], tstart[t] + tcnt[t]); prefixes of a task batch record their task
     int32_t tstart[kP + 1];
     int32_t tcnt[kP];
-    int32_t tbig[kP];
-    int32_t ptask[kP];
-    // prefix batch: values and rows of the (at most two) varying levels
-    int32_t pv0[kP], pv1[kP];
-    long long po0[kP], po1[kP];
-    int32_t pl0[kP], pl1[kP];
-    int32_t pu0[kP], pu1[kP];
+    int32_t ptask[kP];            // task of each prefix (root and task batches)
+    // prefix batch: value and row of the varying level
+    int32_t pv0[kP];
+    long long po0[kP];
+    int32_t pl0[kP];
+    int32_t pu0[kP];
     int32_t pidx[kP];             // index of the prefix in its own set (set batches)
-    const int32_t *bptr[kP];
+    const int32_t *bptr[kP];      // direct: the base range; complement: the single positive operand
     int32_t blen[kP];
-    const int32_t *p1ptr[kP];
-    int32_t p1len[kP];
-    int32_t p1own[kP];            // owner of the P1 row, -1 for a set
+    int32_t p1own[kP];            // complement: owner of that operand's row, -1 for a set
     int32_t pmode[kP];            // -1 skip, 0 direct, 1 complement
     int32_t pdrv[kP];
     uint32_t pcnt[kP];
@@ -80,7 +77,6 @@ struct Lds {
     int16_t seg_prefix[kSeg];
     const int32_t *seg_ptr[kSeg];
     int32_t seg_own[kSeg];
-    unsigned long long acc[kMaxPlansPerLaunch];
     int32_t stop;
     unsigned long long bytes;
 };
@@ -189,25 +185,23 @@ struct Ctx {
     Lds &L;
     int32_t *buf0;  // this wave's scratch (level 2 at offset 0)
     int lane;
-    int vl0, vl1;   // varying levels of the current prefix batch (-1 none)
-    int tmode;      // 1: prefixes are (task, level-2 candidate) pairs of a task batch
+    int vl0;        // the level whose value varies per prefix (-1 none)
+    int tmode;      // 1: levels 0 and 1 come from each prefix's root task (root and task batches)
     int32_t *arena; // this wave's level-2 arena for task batches
+    unsigned long long acc;  // lane p: running count of plan p
 
     __device__ Ctx(const KParams &p, Lds &l, int32_t *b, int ln)
-        : P(p), L(l), buf0(b), lane(ln), vl0(-1), vl1(-1), tmode(0), arena(nullptr) {}
+        : P(p), L(l), buf0(b), lane(ln), vl0(-1), tmode(0), arena(nullptr), acc(0) {}
 
     __device__ __forceinline__ int32_t *setbuf(int level) const { return buf0 + (long long)(level - 2) * P.set_cap; }
 
     __device__ __forceinline__ int32_t val(int y, int l) const {
         if (l < 0) return L.m[y];
-        if (tmode) {
-            if (y == 2) return L.pv0[l];
-            if (y == 0) return L.tu[L.ptask[l]];
-            if (y == 1) return L.tv[L.ptask[l]];
-            return L.m[y];
+        if (tmode && y < 2) {
+            const int t = L.ptask[l];
+            return y == 0 ? L.tu[t] : L.tv[t];
         }
         if (y == vl0) return L.pv0[l];
-        if (y == vl1) return L.pv1[l];
         return L.m[y];
     }
 
@@ -219,21 +213,11 @@ struct Ctx {
             r.n = y == 0 ? L.trl0[t] : L.trl1[t];
             r.up = y == 0 ? L.tru0[t] : L.tru1[t];
             r.owner = y == 0 ? L.tu[t] : L.tv[t];
-        } else if (l >= 0 && tmode && y == 2) {
-            r.p = P.col + L.po0[l];
-            r.n = L.pl0[l];
-            r.up = L.pu0[l];
-            r.owner = L.pv0[l];
         } else if (l >= 0 && y == vl0) {
             r.p = P.col + L.po0[l];
             r.n = L.pl0[l];
             r.up = L.pu0[l];
             r.owner = L.pv0[l];
-        } else if (l >= 0 && y == vl1) {
-            r.p = P.col + L.po1[l];
-            r.n = L.pl1[l];
-            r.up = L.pu1[l];
-            r.owner = L.pv1[l];
         } else {
             r.p = P.col + L.roff[y];
             r.n = L.rlen[y];
@@ -447,9 +431,13 @@ struct Ctx {
             }
             L.pcnt[l] = 0;
             L.pdrv[l] = drv;
-            L.p1ptr[l] = dptr;
-            L.p1len[l] = dlen;
             L.p1own[l] = downer;
+            if (complement) {
+                // the single positive operand is the base or a row: keep it in
+                // the base slots
+                L.bptr[l] = dptr;
+                L.blen[l] = dlen;
+            }
             if (!complement) {
                 L.pmode[l] = 0;
                 L.pconst[l] = 0;
@@ -579,7 +567,7 @@ struct Ctx {
                 } else {
                     // complement term: e in D_k counts if e in P1 and in no
                     // earlier D of this prefix (the segments just before)
-                    ok = in_range(P, L.p1ptr[l], L.p1len[l], L.p1own[l], e);
+                    ok = in_range(P, L.bptr[l], L.blen[l], L.p1own[l], e);
                     for (int s2 = s - 1; ok && s2 >= 0 && L.seg_prefix[s2] == l; s2--)
                         ok = !in_range(P, L.seg_ptr[s2], L.seg_start[s2 + 1] - L.seg_start[s2], L.seg_own[s2], e);
                 }
@@ -621,11 +609,11 @@ struct Ctx {
                 contrib = s;
             }
             if (__ballot(ovf) && lane == 0) atomicOr(P.flags, 1);
-            if (lane == 0) {
-                const unsigned long long a = L.acc[N.plan];
-                const unsigned long long s = a + contrib;
-                if (s < a) atomicOr(P.flags, 1);
-                L.acc[N.plan] = s;
+            // every lane holds the batch total; lane N.plan keeps that plan's sum
+            if (lane == N.plan) {
+                const unsigned long long s = acc + contrib;
+                if (s < acc) atomicOr(P.flags, 1);
+                acc = s;
                 if (P.mode == kModeExists && s > 0) {
                     atomicOr(P.flags + 1, 1);
                     L.stop = 1;
@@ -648,8 +636,8 @@ struct Ctx {
             }
         if (first_enum == 0) return;
         const int32_t *S = setbuf(x);
+        tmode = 0;
         vl0 = x;
-        vl1 = -1;
         for (int32_t s = 0; s < len; s += kP) {
             const int np = min(kP, len - s);
             if (lane < np) {
@@ -706,22 +694,12 @@ struct Ctx {
     // arena take the one-task path afterwards.
     __device__ __forceinline__ void leaf_batch(int eid, int np, unsigned long long okmask) {
         const Node &E = P.nodes[eid];
-        // the task rows as prefix rows (a previous batch's count phase
-        // reused the prefix arrays)
-        if (lane < np) {
-            L.pv0[lane] = L.tu[lane];
-            L.po0[lane] = L.tro0[lane];
-            L.pl0[lane] = L.trl0[lane];
-            L.pu0[lane] = L.tru0[lane];
-            L.pv1[lane] = L.tv[lane];
-            L.po1[lane] = L.tro1[lane];
-            L.pl1[lane] = L.trl1[lane];
-            L.pu1[lane] = L.tru1[lane];
-        }
+        // prefix l is task l here (a previous batch's count phase reused
+        // the task index slots)
+        if (lane < np) L.ptask[lane] = lane;
         wsync();
-        tmode = 0;
-        vl0 = 0;
-        vl1 = 1;
+        tmode = 1;
+        vl0 = -1;
         int32_t dlen = 0;
         const int32_t *dptr = nullptr;
         int drv = -1;
@@ -757,6 +735,7 @@ struct Ctx {
         int tot = 0;
         const int off = wave_scan_excl(dlen, lane, &tot);
         const bool big = ok && (long long)off + dlen > P.arena_cap;
+        const unsigned long long bigmask = __ballot(big);
         const int32_t flen = (ok && !big) ? dlen : 0;
         int total = 0, nseg = 0;
         const int obase = wave_scan_excl(flen, lane, &total);
@@ -769,7 +748,6 @@ struct Ctx {
         if (lane < kP) {
             L.pdrv[lane] = drv;
             L.tcnt[lane] = 0;
-            L.tbig[lane] = big ? 1 : 0;
         }
         if (lane == 0) L.seg_start[nseg] = total;
         wsync();
@@ -815,8 +793,7 @@ struct Ctx {
         if (lane < np) L.tstart[lane] = st;
         if (lane == 0) L.tstart[np] = ntot;
         wsync();
-        vl0 = -1;
-        vl1 = -1;
+        vl0 = 2;
         tmode = 1;
         const int cb = uni(E.child_begin), cc = uni(E.child_count);
         for (int32_t s0 = 0; s0 < ntot; s0 += kP) {
@@ -850,9 +827,10 @@ struct Ctx {
             }
         }
         tmode = 0;
+        vl0 = -1;
         // tasks too large for the arena: one at a time into setbuf(2)
         for (int l = 0; l < np; l++) {
-            if (!L.tbig[l]) continue;
+            if (!(bigmask >> l & 1ull)) continue;
             set_level(0, L.tu[l], 0);
             set_level(1, L.tv[l], 0);
             const int32_t len = materialise(E);
@@ -986,8 +964,8 @@ __device__ bool Ctx<kAV>::av_pass(const AVCheck &c, int x, int l, int32_t e) con
 template <bool kAV>
 __device__ __forceinline__ bool root_ok(Ctx<kAV> &C, const Node &R, int l) {
     const KParams &P = C.P;
-    if (R.label0 >= 0 && (P.lab == nullptr || P.lab[C.L.pv0[l]] != R.label0)) return false;
-    if (R.kind == kRootEdge && R.label1 >= 0 && (P.lab == nullptr || P.lab[C.L.pv1[l]] != R.label1))
+    if (R.label0 >= 0 && (P.lab == nullptr || P.lab[C.L.tu[l]] != R.label0)) return false;
+    if (R.kind == kRootEdge && R.label1 >= 0 && (P.lab == nullptr || P.lab[C.L.tv[l]] != R.label1))
         return false;
     if constexpr (kAV)
         for (int i = 0; i < R.av_count; i++) {
@@ -1008,7 +986,6 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
     int32_t *buf0 = P.scratch ? P.scratch + (long long)blockIdx.x * P.wave_stride : nullptr;
     Ctx<kAV> C(P, L, buf0, lane);
     C.arena = buf0 ? buf0 + P.wave_stride - P.arena_cap : nullptr;
-    for (int i = lane; i < kMaxPlansPerLaunch; i += 64) L.acc[i] = 0;
     if (lane < kMaxLevels) {
         // a valid vertex in every slot of the fixed assignment
         L.m[lane] = 0;
@@ -1062,28 +1039,21 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
                     }
                     L.tu[lane] = u;
                     L.tv[lane] = v;
+                    L.ptask[lane] = lane;
                     const long long ou = P.rp[u];
-                    L.pv0[lane] = u;
-                    L.po0[lane] = ou;
-                    L.pl0[lane] = (int32_t)(P.rp[u + 1] - ou);
-                    L.pu0[lane] = P.up[u];
-                    L.pv1[lane] = v;
                     L.tro0[lane] = ou;
-                    L.trl0[lane] = L.pl0[lane];
-                    L.tru0[lane] = L.pu0[lane];
+                    L.trl0[lane] = (int32_t)(P.rp[u + 1] - ou);
+                    L.tru0[lane] = P.up[u];
                     if (edge_phase) {
                         const long long ov = P.rp[v];
-                        L.po1[lane] = ov;
-                        L.pl1[lane] = (int32_t)(P.rp[v + 1] - ov);
-                        L.pu1[lane] = P.up[v];
                         L.tro1[lane] = ov;
-                        L.trl1[lane] = L.pl1[lane];
-                        L.tru1[lane] = L.pu1[lane];
+                        L.trl1[lane] = (int32_t)(P.rp[v + 1] - ov);
+                        L.tru1[lane] = P.up[v];
                     }
                 }
                 wsync();
-                C.vl0 = 0;
-                C.vl1 = edge_phase ? 1 : -1;
+                C.tmode = 1;
+                C.vl0 = -1;
                 bool okr = false;
                 if (lane < np) okr = root_ok(C, R, lane);
                 const unsigned long long okmask = __ballot(okr);
@@ -1099,8 +1069,8 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
                     wsync();
                     C.count_batch(N, np, -1);
                 }
+                C.tmode = 0;
                 C.vl0 = -1;
-                C.vl1 = -1;
                 if (!any_enum || !edge_phase) continue;
                 // enumeration children with only count children: whole batch
                 bool any_deep = false;
@@ -1131,9 +1101,9 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
         }
     }
     wsync();
-    if (lane < P.n_plans && L.acc[lane]) {
-        const unsigned long long old = atomicAdd(P.counts + lane, L.acc[lane]);
-        if (old + L.acc[lane] < old) atomicOr(P.flags, 1);
+    if (lane < P.n_plans && C.acc) {
+        const unsigned long long old = atomicAdd(P.counts + lane, C.acc);
+        if (old + C.acc < old) atomicOr(P.flags, 1);
     }
     if (lane == 0 && L.bytes) atomicAdd(P.bytes_ctr, L.bytes);
 }
