@@ -55,7 +55,8 @@ def measured_traffic(kernel_hash):
 def cpu_baseline(g, specs, budget_s=15.0):
     """The oracle's generic matcher on a bounded sample of start vertices of
     the same graph: matches/s = (valid maps / |Aut|) / time, over the six
-    induced motifs."""
+    induced motifs.  Start vertices are taken in a seeded random order, in
+    blocks of 16, until the time budget is spent."""
     import numpy as np
     import oracle
     og = oracle.Graph.from_tuple(g)
@@ -63,17 +64,14 @@ def cpu_baseline(g, specs, budget_s=15.0):
     rng = np.random.Generator(np.random.PCG64(99))
     n = og.n
     sample = rng.permutation(n).astype(np.int32)
-    # grow the sample until the budget is used
-    size, spent, matches = 64, 0.0, 0.0
-    used = 0
+    spent, matches, used = 0.0, 0.0, 0
     while spent < budget_s and used < n:
-        roots = sample[used:used + size]
+        roots = sample[used:used + 16]
         t0 = time.perf_counter()
         for s in specs:
             matches += oracle.valid_maps_from(og, s, roots, threads) / oracle.aut(s)
         spent += time.perf_counter() - t0
         used += len(roots)
-        size *= 2
     return {"value": matches / spent, "unit": "matches/s", "cores": threads, "kind": "oracle",
             "sample": f"generic matcher over {used} of {n} random start vertices (pattern vertex 0), "
                       f"6 induced 4-motifs, {spent:.1f} s"}

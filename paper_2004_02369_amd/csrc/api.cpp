@@ -98,7 +98,7 @@ struct pg_graph {
 namespace {
 
 constexpr int64_t kHubMinDegree = 128;
-constexpr long long kArenaInts = 16384;  // per wavefront
+constexpr long long kArenaInts = 32768;  // per wavefront
 constexpr int64_t kHubBudgetBytes = int64_t(1) << 30;
 
 constexpr int kCtlCounts = 0;
@@ -197,7 +197,10 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         radix_sort_u64(keys, 32 + bits_for((uint64_t)n));
         keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
         const int64_t mu = (int64_t)keys.size();
-        if (2 * mu > (int64_t)INT32_MAX * 64) { set_error("graph too large"); return PG_EUNSUPPORTED; }
+        if (2 * mu > (int64_t)INT32_MAX) {
+            set_error("graph too large: more than 2^31 - 1 adjacency entries");
+            return PG_EUNSUPPORTED;
+        }
 
         // 2. degree order: rank by (degree, original id) ascending (Sec. 5.2)
         std::vector<int64_t> deg(n, 0);
@@ -496,6 +499,7 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     std::memset(&P, 0, sizeof(P));
     P.rp = g->rp;
     P.col = g->col;
+    P.ncol = 2 * g->m;
     P.up = g->up;
     P.hub_bits = g->hub_bits;
     P.hub_words = g->hub_words;

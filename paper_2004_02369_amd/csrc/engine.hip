@@ -36,14 +36,14 @@
 namespace pg {
 
 constexpr int kP = 64;        // prefixes per flattened batch (one per lane)
-constexpr int kMaxDiffB = 2;  // complement counting handles up to this many difference rows
+constexpr int kMaxDiffB = 3;  // complement counting handles up to this many difference rows
 constexpr int kSeg = kP * kMaxDiffB;
 constexpr int kBaseOp = 31;   // operand id of the base set
 
 struct Lds {
     // the fixed assignment (levels matched so far) and their rows
     int32_t m[kMaxLevels];
-    long long roff[kMaxLevels];
+    int32_t roff[kMaxLevels];     // row offsets in col (the graph has < 2^31 entries)
     int32_t rlen[kMaxLevels];
     int32_t rup[kMaxLevels];      // index of the first neighbour above the row's owner
     int32_t cur_idx[kMaxLevels];  // index of m[level] in that level's materialised set
@@ -51,31 +51,33 @@ struct Lds {
     int32_t st_node[kMaxLevels];
     int32_t st_idx[kMaxLevels];
     int32_t st_child[kMaxLevels];
-    // root tasks of the current batch and their rows (levels 0 and 1)
+    // parent slots: root tasks (levels 0 and 1) or elements of a
+    // materialised set (one level), with their rows
     int32_t tu[kP], tv[kP];
-    long long tro0[kP], tro1[kP];
+    int32_t tidx[kP];             // set parents: index of the parent in its set
+    int32_t tro0[kP], tro1[kP];
     int32_t trl0[kP], trl1[kP], tru0[kP], tru1[kP];
     // level-2 candidates of a whole task batch, in the arena: task t owns
     // [tstart[t], tstart[t] + tcnt[t]); prefixes of a task batch record their task
     int32_t tstart[kP + 1];
     int32_t tcnt[kP];
-    int32_t ptask[kP];            // task of each prefix (root and task batches)
+    int32_t ptask[kP];            // parent slot of each prefix
     // prefix batch: value and row of the varying level
     int32_t pv0[kP];
-    long long po0[kP];
+    int32_t po0[kP];
     int32_t pl0[kP];
     int32_t pu0[kP];
     int32_t pidx[kP];             // index of the prefix in its own set (set batches)
-    const int32_t *bptr[kP];      // direct: the base range; complement: the single positive operand
+    int32_t boff[kP];             // direct: the base range; complement: the single positive operand (enc)
     int32_t blen[kP];
     int32_t p1own[kP];            // complement: owner of that operand's row, -1 for a set
-    int32_t pmode[kP];            // -1 skip, 0 direct, 1 complement
-    int32_t pdrv[kP];
+    int8_t pmode[kP];             // -1 skip, 0 direct, 1 complement
+    int8_t pdrv[kP];
     uint32_t pcnt[kP];
     int32_t pconst[kP];
     int32_t seg_start[kSeg + 1];
-    int16_t seg_prefix[kSeg];
-    const int32_t *seg_ptr[kSeg];
+    uint8_t seg_prefix[kSeg];
+    int32_t seg_off[kSeg];        // segment start (enc)
     int32_t seg_own[kSeg];
     int32_t stop;
     unsigned long long bytes;
@@ -186,33 +188,43 @@ struct Ctx {
     int32_t *buf0;  // this wave's scratch (level 2 at offset 0)
     int lane;
     int vl0;        // the level whose value varies per prefix (-1 none)
-    int tmode;      // 1: levels 0 and 1 come from each prefix's root task (root and task batches)
-    int32_t *arena; // this wave's level-2 arena for task batches
+    int plev0;      // levels taken from each prefix's parent slot (-1 none):
+    int plev1;      //   root tasks give levels 0 and 1, set parents one level
+    int amode;      // 1: the vl0 level's set is the arena slice of the prefix's parent
+    int32_t *arena; // this wave's arena for batched expansions
     unsigned long long acc;  // lane p: running count of plan p
 
     __device__ Ctx(const KParams &p, Lds &l, int32_t *b, int ln)
-        : P(p), L(l), buf0(b), lane(ln), vl0(-1), tmode(0), arena(nullptr), acc(0) {}
+        : P(p), L(l), buf0(b), lane(ln), vl0(-1), plev0(-1), plev1(-1), amode(0), arena(nullptr), acc(0) {}
 
     __device__ __forceinline__ int32_t *setbuf(int level) const { return buf0 + (long long)(level - 2) * P.set_cap; }
 
+    // 32-bit addresses kept in LDS: rows as offsets into col, sets as the
+    // complement of their offset in this wave's scratch
+    __device__ __forceinline__ int32_t enc(const int32_t *p) const {
+        return (p >= P.col && p < P.col + P.ncol) ? (int32_t)(p - P.col) : ~(int32_t)(p - buf0);
+    }
+    __device__ __forceinline__ const int32_t *dec(int32_t o) const {
+        return o >= 0 ? P.col + o : buf0 + (long long)(~o);
+    }
+
     __device__ __forceinline__ int32_t val(int y, int l) const {
         if (l < 0) return L.m[y];
-        if (tmode && y < 2) {
-            const int t = L.ptask[l];
-            return y == 0 ? L.tu[t] : L.tv[t];
-        }
+        if (y == plev0) return L.tu[L.ptask[l]];
+        if (y == plev1) return L.tv[L.ptask[l]];
         if (y == vl0) return L.pv0[l];
         return L.m[y];
     }
 
     __device__ __forceinline__ RowRef row(int y, int l) const {
         RowRef r;
-        if (l >= 0 && tmode && y < 2) {
+        if (l >= 0 && (y == plev0 || y == plev1)) {
             const int t = L.ptask[l];
-            r.p = P.col + (y == 0 ? L.tro0[t] : L.tro1[t]);
-            r.n = y == 0 ? L.trl0[t] : L.trl1[t];
-            r.up = y == 0 ? L.tru0[t] : L.tru1[t];
-            r.owner = y == 0 ? L.tu[t] : L.tv[t];
+            const bool a = y == plev0;
+            r.p = P.col + (a ? L.tro0[t] : L.tro1[t]);
+            r.n = a ? L.trl0[t] : L.trl1[t];
+            r.up = a ? L.tru0[t] : L.tru1[t];
+            r.owner = a ? L.tu[t] : L.tv[t];
         } else if (l >= 0 && y == vl0) {
             r.p = P.col + L.po0[l];
             r.n = L.pl0[l];
@@ -225,6 +237,42 @@ struct Ctx {
             r.owner = L.m[y];
         }
         return r;
+    }
+
+    // Range of node N's base set for prefix l (-1: fixed assignment) within
+    // (lo, hi).  The base set is the prefix's own set (level vl0, in the
+    // arena slice of its parent when amode), the parent's set (level
+    // plev0), or a fixed level's set; a bound equal to the element the
+    // prefix holds in that set is its known index.
+    __device__ __forceinline__ int32_t base_range(const Node &N, int l, int32_t lo, int32_t hi,
+                                                  const int32_t **bp) const {
+        const int bl = N.base;
+        const int32_t *B;
+        int32_t Bn, cur, ci;
+        if (l >= 0 && bl == vl0) {
+            B = amode ? arena + L.tstart[L.ptask[l]] : setbuf(bl);
+            Bn = amode ? L.tcnt[L.ptask[l]] : L.set_len[bl];
+            cur = L.pv0[l];
+            ci = L.pidx[l];
+        } else if (l >= 0 && bl == plev0) {
+            B = setbuf(bl);
+            Bn = L.set_len[bl];
+            cur = L.tu[L.ptask[l]];
+            ci = L.tidx[L.ptask[l]];
+        } else {
+            B = setbuf(bl);
+            Bn = L.set_len[bl];
+            cur = L.m[bl];
+            ci = L.cur_idx[bl];
+        }
+        if (lo >= hi - 1) {
+            *bp = B;
+            return 0;
+        }
+        const int32_t b = lo < 0 ? 0 : (lo == cur ? ci + 1 : lower_bound(B, Bn, lo + 1));
+        const int32_t e = hi == INT_MAX ? Bn : (hi == cur ? ci : lower_bound(B, Bn, hi));
+        *bp = B + b;
+        return e > b ? e - b : 0;
     }
 
     __device__ __forceinline__ RowRef vrow(int32_t v) const {
@@ -271,18 +319,7 @@ struct Ctx {
         int drv = -1;
         long long bytes = 0;
         if (N.base >= 0) {
-            const int32_t *B = setbuf(N.base);
-            const int32_t Bn = L.set_len[N.base];
-            const int32_t cur = L.m[N.base], ci = L.cur_idx[N.base];
-            int32_t b, e;
-            if (lo >= hi - 1) {
-                b = e = 0;
-            } else {
-                b = lo < 0 ? 0 : (lo == cur ? ci + 1 : lower_bound(B, Bn, lo + 1));
-                e = hi == INT_MAX ? Bn : (hi == cur ? ci : lower_bound(B, Bn, hi));
-            }
-            bp = B + b;
-            bn = e > b ? e - b : 0;
+            bn = base_range(N, -1, lo, hi, &bp);
             dptr = bp;
             dlen = bn;
             drv = kBaseOp;
@@ -331,10 +368,9 @@ struct Ctx {
 
     // ---------------------------------------------------------------
     // Flattened evaluation of count / emit node N (level x) over np
-    // prefixes already loaded into the batch arrays (pv*, po*, pl*, pu*,
-    // pmode; pidx when own >= 0: the prefixes are the elements of level
-    // own's set, so a base range bounded by the prefix itself is known).
-    __device__ __forceinline__ void count_batch(const Node &N, int np, int own) {
+    // prefixes already loaded into the batch arrays (pv0/po0/pl0/pu0 and
+    // pidx for the varying level vl0, ptask for parent-slot levels, pmode).
+    __device__ __forceinline__ void count_batch(const Node &N, int np) {
         const int x = N.level;
         const bool emit = N.kind == kEmit;
         int my_nseg = 0, my_tot = 0;
@@ -351,29 +387,11 @@ struct Ctx {
             int drv = -1, downer = -1;
             long long bytes = 0;
             if (N.base >= 0) {
-                // in a task batch the only materialised level is 2: the
-                // prefix's task slice of the arena
-                const int32_t *B = tmode ? arena + L.tstart[L.ptask[l]] : setbuf(N.base);
-                const int32_t Bn = tmode ? L.tcnt[L.ptask[l]] : L.set_len[N.base];
-                int32_t b, e;
-                if (lo >= hi - 1) {
-                    b = e = 0;
-                } else if (N.base == own) {
-                    const int32_t i = L.pidx[l], pv = L.pv0[l];
-                    b = lo < 0 ? 0 : (lo == pv ? i + 1 : lower_bound(B, Bn, lo + 1));
-                    e = hi == INT_MAX ? Bn : (hi == pv ? i : lower_bound(B, Bn, hi));
-                } else if (tmode) {
-                    b = lo < 0 ? 0 : lower_bound(B, Bn, lo + 1);
-                    e = hi == INT_MAX ? Bn : lower_bound(B, Bn, hi);
-                } else {
-                    const int32_t cur = L.m[N.base], ci = L.cur_idx[N.base];
-                    b = lo < 0 ? 0 : (lo == cur ? ci + 1 : lower_bound(B, Bn, lo + 1));
-                    e = hi == INT_MAX ? Bn : (hi == cur ? ci : lower_bound(B, Bn, hi));
-                }
-                const int32_t n = e > b ? e - b : 0;
-                L.bptr[l] = B + b;
+                const int32_t *bp;
+                const int32_t n = base_range(N, l, lo, hi, &bp);
+                L.boff[l] = enc(bp);
                 L.blen[l] = n;
-                dptr = B + b;
+                dptr = bp;
                 dlen = n;
                 drv = kBaseOp;
                 bytes += n;
@@ -430,12 +448,12 @@ struct Ctx {
                 atomicAdd(&L.bytes, 4ull * (unsigned long long)bytes);
             }
             L.pcnt[l] = 0;
-            L.pdrv[l] = drv;
+            L.pdrv[l] = (int8_t)drv;
             L.p1own[l] = downer;
             if (complement) {
                 // the single positive operand is the base or a row: keep it in
                 // the base slots
-                L.bptr[l] = dptr;
+                L.boff[l] = enc(dptr);
                 L.blen[l] = dlen;
             }
             if (!complement) {
@@ -517,23 +535,23 @@ struct Ctx {
         int obase = wave_scan_excl(my_tot, lane, &total);
         if (my_nseg > 0) {
             L.seg_start[sbase] = obase;
-            L.seg_prefix[sbase] = (int16_t)lane;
+            L.seg_prefix[sbase] = (uint8_t)lane;
             L.seg_own[sbase] = so0;
-            L.seg_ptr[sbase] = sp0;
+            L.seg_off[sbase] = enc(sp0);
             obase += sl0;
         }
         if (my_nseg > 1) {
             L.seg_start[sbase + 1] = obase;
-            L.seg_prefix[sbase + 1] = (int16_t)lane;
+            L.seg_prefix[sbase + 1] = (uint8_t)lane;
             L.seg_own[sbase + 1] = so1;
-            L.seg_ptr[sbase + 1] = sp1;
+            L.seg_off[sbase + 1] = enc(sp1);
             obase += sl1;
         }
         if (my_nseg > 2) {
             L.seg_start[sbase + 2] = obase;
-            L.seg_prefix[sbase + 2] = (int16_t)lane;
+            L.seg_prefix[sbase + 2] = (uint8_t)lane;
             L.seg_own[sbase + 2] = so2;
-            L.seg_ptr[sbase + 2] = sp2;
+            L.seg_off[sbase + 2] = enc(sp2);
         }
         if (lane == 0) L.seg_start[nseg] = total;
         wsync();
@@ -561,15 +579,15 @@ struct Ctx {
                     while (L.seg_start[s + 1] <= t) s++;
                 }
                 l = L.seg_prefix[s];
-                e = L.seg_ptr[s][t - L.seg_start[s]];
+                e = dec(L.seg_off[s])[t - L.seg_start[s]];
                 if (L.pmode[l] == 0) {
-                    ok = test_direct(N, x, l, L.pdrv[l], e, L.bptr[l], L.blen[l]);
+                    ok = test_direct(N, x, l, L.pdrv[l], e, dec(L.boff[l]), L.blen[l]);
                 } else {
                     // complement term: e in D_k counts if e in P1 and in no
                     // earlier D of this prefix (the segments just before)
-                    ok = in_range(P, L.bptr[l], L.blen[l], L.p1own[l], e);
+                    ok = in_range(P, dec(L.boff[l]), L.blen[l], L.p1own[l], e);
                     for (int s2 = s - 1; ok && s2 >= 0 && L.seg_prefix[s2] == l; s2--)
-                        ok = !in_range(P, L.seg_ptr[s2], L.seg_start[s2 + 1] - L.seg_start[s2], L.seg_own[s2], e);
+                        ok = !in_range(P, dec(L.seg_off[s2]), L.seg_start[s2 + 1] - L.seg_start[s2], L.seg_own[s2], e);
                 }
             }
             if (emit) {
@@ -636,7 +654,9 @@ struct Ctx {
             }
         if (first_enum == 0) return;
         const int32_t *S = setbuf(x);
-        tmode = 0;
+        const int sp0 = plev0, sp1 = plev1;
+        plev0 = plev1 = -1;
+        amode = 0;
         vl0 = x;
         for (int32_t s = 0; s < len; s += kP) {
             const int np = min(kP, len - s);
@@ -644,7 +664,7 @@ struct Ctx {
                 const int32_t v = S[s + lane];
                 const long long o = P.rp[v];
                 L.pv0[lane] = v;
-                L.po0[lane] = o;
+                L.po0[lane] = (int32_t)o;
                 L.pl0[lane] = (int32_t)(P.rp[v + 1] - o);
                 L.pu0[lane] = P.up[v];
                 L.pidx[lane] = s + lane;
@@ -652,17 +672,19 @@ struct Ctx {
             for (int c = 0; c < first_enum; c++) {
                 if (lane < np) L.pmode[lane] = 0;
                 wsync();
-                count_batch(P.nodes[cb + c], np, x);
+                count_batch(P.nodes[cb + c], np);
             }
         }
         vl0 = -1;
+        plev0 = sp0;
+        plev1 = sp1;
     }
 
     __device__ __forceinline__ void set_level(int x, int32_t v, int32_t idx) {
         if (lane == 0) {
             const long long o = P.rp[v];
             L.m[x] = v;
-            L.roff[x] = o;
+            L.roff[x] = (int32_t)o;
             L.rlen[x] = (int32_t)(P.rp[v + 1] - o);
             L.rup[x] = P.up[v];
             L.cur_idx[x] = idx;
@@ -686,22 +708,28 @@ struct Ctx {
         return false;
     }
 
-    // Level-2 enumeration node E whose children are all count / emit nodes,
-    // for a whole batch of np edge tasks at once: one flattened pass
-    // materialises every task's candidates into the arena (in task order,
-    // each task's slice sorted), then the count children run flattened over
-    // all (task, candidate) prefixes.  Tasks whose driver does not fit the
-    // arena take the one-task path afterwards.
+    __device__ __forceinline__ bool is_leaf_enum(const Node &E) const {
+        return E.kind == kEnum && !has_enum_child(E) && !(P.run_flags & PG_RUN_NO_TASK_BATCH);
+    }
+
+    // Enumeration node E whose children are all count / emit nodes, for a
+    // batch of np parents at once (slots 0..np-1: root tasks with plev0/1 =
+    // levels 0/1, or elements of a materialised set with plev0 = its
+    // level): one flattened pass materialises every parent's candidates
+    // into the arena (parent order, each slice sorted), then the count
+    // children run flattened over all (parent, candidate) prefixes.
+    // Parents whose driver does not fit the arena take the one-parent path.
     __device__ __forceinline__ void leaf_batch(int eid, int np, unsigned long long okmask) {
         const Node &E = P.nodes[eid];
-        // prefix l is task l here (a previous batch's count phase reused
-        // the task index slots)
+        const int x = E.level;
         if (lane < np) L.ptask[lane] = lane;
         wsync();
-        tmode = 1;
         vl0 = -1;
+        amode = 0;
         int32_t dlen = 0;
         const int32_t *dptr = nullptr;
+        const int32_t *my_bp = nullptr;  // this parent's base range (kept across rounds)
+        int32_t my_bn = 0;
         int drv = -1;
         const bool ok = lane < np && (okmask >> lane & 1ull);
         if (ok) {
@@ -710,6 +738,13 @@ struct Ctx {
             for (uint32_t s = E.hi; s; s &= s - 1) hi = min(hi, val(__builtin_ctz(s), lane));
             dlen = INT_MAX;
             long long bytes = 0;
+            if (E.base >= 0) {
+                my_bn = base_range(E, lane, lo, hi, &my_bp);
+                dlen = my_bn;
+                dptr = my_bp;
+                drv = kBaseOp;
+                bytes += my_bn;
+            }
             for (uint32_t s = E.t_isect; s; s &= s - 1) {
                 const int y = __builtin_ctz(s);
                 RowRef r = row(y, lane);
@@ -732,130 +767,193 @@ struct Ctx {
                 atomicAdd(&L.bytes, 4ull * (unsigned long long)bytes);
             }
         }
-        int tot = 0;
-        const int off = wave_scan_excl(dlen, lane, &tot);
-        const bool big = ok && (long long)off + dlen > P.arena_cap;
+        // parents whose own driver exceeds the arena go one at a time below;
+        // the rest run in rounds of as many parents as fit the arena
+        const bool big = ok && dlen > P.arena_cap;
         const unsigned long long bigmask = __ballot(big);
-        const int32_t flen = (ok && !big) ? dlen : 0;
-        int total = 0, nseg = 0;
-        const int obase = wave_scan_excl(flen, lane, &total);
-        const int sidx = wave_scan_excl(flen > 0 ? 1 : 0, lane, &nseg);
-        if (flen > 0) {
-            L.seg_start[sidx] = obase;
-            L.seg_prefix[sidx] = (int16_t)lane;
-            L.seg_ptr[sidx] = dptr;
-        }
-        if (lane < kP) {
-            L.pdrv[lane] = drv;
+        unsigned long long remaining = __ballot(ok && !big);
+        while (remaining) {
+            // parent slots as the materialisation pass reads them (a previous
+            // round's count phase reused these arrays)
+            L.pdrv[lane] = (int8_t)drv;
+            L.boff[lane] = my_bp ? enc(my_bp) : 0;
+            L.blen[lane] = my_bn;
+            const bool mine = (remaining >> lane) & 1ull;
+            int tot = 0;
+            const int off = wave_scan_excl(mine ? dlen : 0, lane, &tot);
+            const bool sel = mine && (long long)off + dlen <= P.arena_cap;
+            const unsigned long long selmask = __ballot(sel);
+            remaining &= ~selmask;
+            const int32_t flen = sel ? dlen : 0;
+            int total = 0, nseg = 0;
+            const int obase = wave_scan_excl(flen, lane, &total);
+            const int sidx = wave_scan_excl(flen > 0 ? 1 : 0, lane, &nseg);
+            wsync();
+            if (flen > 0) {
+                L.seg_start[sidx] = obase;
+                L.seg_prefix[sidx] = (uint8_t)lane;
+                L.seg_off[sidx] = enc(dptr);
+            }
             L.tcnt[lane] = 0;
-        }
-        if (lane == 0) L.seg_start[nseg] = total;
-        wsync();
-        int32_t out_n = 0;
-        int s = 0;
-        for (int32_t tb = 0; tb < total; tb += 64) {
-            const int32_t t = tb + lane;
-            bool pass = false;
-            int l = 0;
-            int32_t e = 0;
-            if (t < total) {
-                if (tb == 0) {
-                    int s_lo = 0, s_n = nseg;
-                    while (s_n > 1) {
-                        const int half = s_n >> 1;
-                        if (L.seg_start[s_lo + half] <= t) {
-                            s_lo += half;
-                            s_n -= half;
+            if (lane == 0) L.seg_start[nseg] = total;
+            wsync();
+            int32_t out_n = 0;
+            int s = 0;
+            for (int32_t tb = 0; tb < total; tb += 64) {
+                const int32_t t = tb + lane;
+                bool pass = false;
+                int l = 0;
+                int32_t e = 0;
+                if (t < total) {
+                    if (tb == 0) {
+                        int s_lo = 0, s_n = nseg;
+                        while (s_n > 1) {
+                            const int half = s_n >> 1;
+                            if (L.seg_start[s_lo + half] <= t) {
+                                s_lo += half;
+                                s_n -= half;
+                            } else {
+                                s_n = half;
+                            }
+                        }
+                        s = s_lo;
+                    } else {
+                        while (L.seg_start[s + 1] <= t) s++;
+                    }
+                    l = L.seg_prefix[s];
+                    e = dec(L.seg_off[s])[t - L.seg_start[s]];
+                    pass = test_direct(E, x, l, L.pdrv[l], e, dec(L.boff[l]), L.blen[l]);
+                }
+                const unsigned long long bal = __ballot(pass);
+                if (pass) {
+                    arena[out_n + (int32_t)__popcll(bal & ((1ull << lane) - 1ull))] = e;
+                    atomicAdd(&L.tcnt[l], 1);
+                }
+                out_n += (int32_t)__popcll(bal);
+            }
+            wsync();
+            // survivors are in parent order: slices start at the scan of the counts
+            int ntot = 0;
+            const int32_t tc = lane < np ? L.tcnt[lane] : 0;
+            const int32_t st = wave_scan_excl(tc, lane, &ntot);
+            if (lane < np) L.tstart[lane] = st;
+            if (lane == 0) L.tstart[np] = ntot;
+            wsync();
+            vl0 = x;
+            amode = 1;
+            const int cb = uni(E.child_begin), cc = uni(E.child_count);
+            for (int32_t s0 = 0; s0 < ntot; s0 += kP) {
+                const int np2 = min(kP, ntot - s0);
+                if (lane < np2) {
+                    const int32_t idx = s0 + lane;
+                    // parent holding arena index idx: last t with tstart[t] <= idx
+                    int t_lo = 0, t_n = np;
+                    while (t_n > 1) {
+                        const int half = t_n >> 1;
+                        if (L.tstart[t_lo + half] <= idx) {
+                            t_lo += half;
+                            t_n -= half;
                         } else {
-                            s_n = half;
+                            t_n = half;
                         }
                     }
-                    s = s_lo;
-                } else {
-                    while (L.seg_start[s + 1] <= t) s++;
+                    const int32_t v = arena[idx];
+                    const long long o = P.rp[v];
+                    L.ptask[lane] = t_lo;
+                    L.pidx[lane] = idx - L.tstart[t_lo];
+                    L.pv0[lane] = v;
+                    L.po0[lane] = (int32_t)o;
+                    L.pl0[lane] = (int32_t)(P.rp[v + 1] - o);
+                    L.pu0[lane] = P.up[v];
                 }
-                l = L.seg_prefix[s];
-                e = L.seg_ptr[s][t - L.seg_start[s]];
-                pass = test_direct(E, 2, l, L.pdrv[l], e, nullptr, 0);
-            }
-            const unsigned long long bal = __ballot(pass);
-            if (pass) {
-                arena[out_n + (int32_t)__popcll(bal & ((1ull << lane) - 1ull))] = e;
-                atomicAdd(&L.tcnt[l], 1);
-            }
-            out_n += (int32_t)__popcll(bal);
-        }
-        wsync();
-        // survivors are in task order: slices start at the scan of the counts
-        int ntot = 0;
-        const int32_t tc = lane < np ? L.tcnt[lane] : 0;
-        const int32_t st = wave_scan_excl(tc, lane, &ntot);
-        if (lane < np) L.tstart[lane] = st;
-        if (lane == 0) L.tstart[np] = ntot;
-        wsync();
-        vl0 = 2;
-        tmode = 1;
-        const int cb = uni(E.child_begin), cc = uni(E.child_count);
-        for (int32_t s0 = 0; s0 < ntot; s0 += kP) {
-            const int np2 = min(kP, ntot - s0);
-            if (lane < np2) {
-                const int32_t idx = s0 + lane;
-                // task holding arena index idx: last t with tstart[t] <= idx
-                int t_lo = 0, t_n = np;
-                while (t_n > 1) {
-                    const int half = t_n >> 1;
-                    if (L.tstart[t_lo + half] <= idx) {
-                        t_lo += half;
-                        t_n -= half;
-                    } else {
-                        t_n = half;
-                    }
+                for (int c = 0; c < cc; c++) {
+                    if (lane < np2) L.pmode[lane] = 0;
+                    wsync();
+                    count_batch(P.nodes[cb + c], np2);
                 }
-                const int32_t v = arena[idx];
-                const long long o = P.rp[v];
-                L.ptask[lane] = t_lo;
-                L.pidx[lane] = idx - L.tstart[t_lo];
-                L.pv0[lane] = v;
-                L.po0[lane] = o;
-                L.pl0[lane] = (int32_t)(P.rp[v + 1] - o);
-                L.pu0[lane] = P.up[v];
             }
-            for (int c = 0; c < cc; c++) {
-                if (lane < np2) L.pmode[lane] = 0;
-                wsync();
-                count_batch(P.nodes[cb + c], np2, 2);
-            }
-        }
-        tmode = 0;
-        vl0 = -1;
-        // tasks too large for the arena: one at a time into setbuf(2)
-        for (int l = 0; l < np; l++) {
-            if (!(bigmask >> l & 1ull)) continue;
-            set_level(0, L.tu[l], 0);
-            set_level(1, L.tv[l], 0);
-            const int32_t len = materialise(E);
-            if (lane == 0) L.set_len[2] = len;
+            amode = 0;
+            vl0 = -1;
+            // the next round's setup reads parent slots through ptask
+            if (lane < np) L.ptask[lane] = lane;
             wsync();
-            if (len > 0) counts_over_set(eid, 2, len);
+        }
+        // parents too large for the arena: one at a time into setbuf(x)
+        if (bigmask) {
+            const int sp0 = plev0, sp1 = plev1;
+            for (int l = 0; l < np; l++) {
+                if (!(bigmask >> l & 1ull)) continue;
+                if (sp0 >= 0) set_level(sp0, L.tu[l], L.tidx[l]);
+                if (sp1 >= 0) set_level(sp1, L.tv[l], 0);
+                plev0 = plev1 = -1;
+                const int32_t len = materialise(E);
+                if (lane == 0) L.set_len[x] = len;
+                wsync();
+                if (len > 0) counts_over_set(eid, x, len);
+                plev0 = sp0;
+                plev1 = sp1;
+            }
         }
     }
 
-    // depth-first walk of the enumeration children of root node rid that
-    // have enumeration children themselves (the others run as task batches),
-    // with levels 0..1 already assigned in m[]
+    // the leaf enumeration children of node nid (level x, set S_x of length
+    // len materialised), batched over S_x in groups of 64 parents
+    __device__ __forceinline__ void leaf_children_over_set(int nid, int x, int32_t len) {
+        const Node &N = P.nodes[nid];
+        const int cb = uni(N.child_begin), cc = uni(N.child_count);
+        const int32_t *S = setbuf(x);
+        for (int c = 0; c < cc; c++) {
+            const int eid = cb + c;
+            if (!is_leaf_enum(P.nodes[eid])) continue;
+            for (int32_t s0 = 0; s0 < len; s0 += kP) {
+                if (stopped()) return;
+                const int np = min(kP, len - s0);
+                if (lane < np) {
+                    const int32_t v = S[s0 + lane];
+                    const long long o = P.rp[v];
+                    L.tu[lane] = v;
+                    L.tidx[lane] = s0 + lane;
+                    L.tro0[lane] = (int32_t)o;
+                    L.trl0[lane] = (int32_t)(P.rp[v + 1] - o);
+                    L.tru0[lane] = P.up[v];
+                }
+                wsync();
+                plev0 = x;
+                plev1 = -1;
+                leaf_batch(eid, np, np == 64 ? ~0ull : ((1ull << np) - 1ull));
+                plev0 = -1;
+            }
+        }
+    }
+
+    __device__ __forceinline__ bool has_deep_enum_child(const Node &N) const {
+        for (int c = 0; c < N.child_count; c++) {
+            const Node &E = P.nodes[N.child_begin + c];
+            if (E.kind == kEnum && !is_leaf_enum(E)) return true;
+        }
+        return false;
+    }
+
+    // depth-first walk of the deep enumeration children of root node rid
+    // (those with enumeration children of their own; leaf ones run as
+    // batches), with levels 0..1 already assigned in m[].  Each frame holds a
+    // materialised set; its count children and leaf enumeration children run
+    // batched over the whole set, its deep enumeration children per element.
     __device__ __forceinline__ void dfs(int rid) {
         const Node &R = P.nodes[rid];
         const int cb = uni(R.child_begin), cc = uni(R.child_count);
         for (int c = 0; c < cc; c++) {
             const int e0 = cb + c;
-            if (P.nodes[e0].kind != kEnum) continue;
-            if (!has_enum_child(P.nodes[e0]) && !(P.run_flags & PG_RUN_NO_TASK_BATCH)) continue;
+            const Node &E0 = P.nodes[e0];
+            if (E0.kind != kEnum || is_leaf_enum(E0)) continue;
             if (stopped()) return;
-            const int32_t len = materialise(P.nodes[e0]);
+            const int32_t len = materialise(E0);
             if (lane == 0) L.set_len[2] = len;
             wsync();
             if (len == 0) continue;
             counts_over_set(e0, 2, len);
+            leaf_children_over_set(e0, 2, len);
+            if (!has_deep_enum_child(E0)) continue;
             // stack of enumeration frames
             if (lane == 0) {
                 L.st_node[0] = e0;
@@ -873,8 +971,8 @@ struct Ctx {
                 const int ncb = uni(N.child_begin), ncc = uni(N.child_count);
                 int ch = uni(L.st_child[f]);
                 const int idx = uni(L.st_idx[f]);
-                // advance to the next enumeration child
-                while (ch < ncc && P.nodes[ncb + ch].kind != kEnum) ch++;
+                // advance to the next deep enumeration child
+                while (ch < ncc && (P.nodes[ncb + ch].kind != kEnum || is_leaf_enum(P.nodes[ncb + ch]))) ch++;
                 if (ch >= ncc) {
                     if (idx + 1 >= L.set_len[x]) {
                         sp--;
@@ -896,7 +994,8 @@ struct Ctx {
                 wsync();
                 if (len2 == 0) continue;
                 counts_over_set(nid2, x + 1, len2);
-                if (has_enum_child(P.nodes[nid2])) {
+                leaf_children_over_set(nid2, x + 1, len2);
+                if (has_deep_enum_child(P.nodes[nid2])) {
                     if (lane == 0) {
                         L.st_node[sp] = nid2;
                         L.st_idx[sp] = 0;
@@ -980,7 +1079,7 @@ __device__ __forceinline__ bool root_ok(Ctx<kAV> &C, const Node &R, int l) {
 // kAV: the trie holds anti-vertex checks (the variant without them keeps
 // the out-of-line check and its call frame out of the hot loops)
 template <bool kAV>
-__global__ void __launch_bounds__(64) match_kernel(KParams P) {
+__device__ __forceinline__ void match_body(const KParams P) {
     __shared__ Lds L;
     const int lane = threadIdx.x;
     int32_t *buf0 = P.scratch ? P.scratch + (long long)blockIdx.x * P.wave_stride : nullptr;
@@ -1039,20 +1138,26 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
                     }
                     L.tu[lane] = u;
                     L.tv[lane] = v;
+                    L.tidx[lane] = 0;
                     L.ptask[lane] = lane;
                     const long long ou = P.rp[u];
-                    L.tro0[lane] = ou;
+                    L.tro0[lane] = (int32_t)ou;
                     L.trl0[lane] = (int32_t)(P.rp[u + 1] - ou);
                     L.tru0[lane] = P.up[u];
                     if (edge_phase) {
                         const long long ov = P.rp[v];
-                        L.tro1[lane] = ov;
+                        L.tro1[lane] = (int32_t)ov;
                         L.trl1[lane] = (int32_t)(P.rp[v + 1] - ov);
                         L.tru1[lane] = P.up[v];
                     }
                 }
                 wsync();
-                C.tmode = 1;
+                // the batch's root tasks also stay in registers (lane l holds
+                // task l): deeper batches reuse the parent slots
+                const int32_t task_u = lane < np ? L.tu[lane] : 0;
+                const int32_t task_v = lane < np ? L.tv[lane] : 0;
+                C.plev0 = 0;
+                C.plev1 = edge_phase ? 1 : -1;
                 C.vl0 = -1;
                 bool okr = false;
                 if (lane < np) okr = root_ok(C, R, lane);
@@ -1065,30 +1170,32 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
                         any_enum = true;
                         break;
                     }
-                    if (lane < np) L.pmode[lane] = okr ? 0 : -1;
+                    if (lane < np) L.pmode[lane] = okr ? (int8_t)0 : (int8_t)-1;
                     wsync();
-                    C.count_batch(N, np, -1);
+                    C.count_batch(N, np);
                 }
-                C.tmode = 0;
-                C.vl0 = -1;
-                if (!any_enum || !edge_phase) continue;
+                if (!any_enum || !edge_phase) {
+                    C.plev0 = C.plev1 = -1;
+                    continue;
+                }
                 // enumeration children with only count children: whole batch
                 bool any_deep = false;
                 for (int c = 0; c < cc; c++) {
                     const int eid = cb + c;
                     if (P.nodes[eid].kind != kEnum) continue;
-                    if (C.has_enum_child(P.nodes[eid]) || (P.run_flags & PG_RUN_NO_TASK_BATCH)) {
+                    if (!C.is_leaf_enum(P.nodes[eid])) {
                         any_deep = true;
                         continue;
                     }
                     if (C.stopped()) break;
                     C.leaf_batch(eid, np, okmask);
                 }
+                C.plev0 = C.plev1 = -1;
                 // deeper enumeration children: one task at a time
                 if (!any_deep) continue;
                 for (int l = 0; l < np; l++) {
                     if (!(okmask >> l & 1ull)) continue;
-                    const int32_t u = L.tu[l], v = L.tv[l];
+                    const int32_t u = __shfl(task_u, l), v = __shfl(task_v, l);
                     wsync();
                     C.set_level(0, u, 0);
                     C.set_level(1, v, 0);
@@ -1108,17 +1215,24 @@ __global__ void __launch_bounds__(64) match_kernel(KParams P) {
     if (lane == 0 && L.bytes) atomicAdd(P.bytes_ctr, L.bytes);
 }
 
+// the common variant is held to 128 VGPRs: four wavefronts per SIMD
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) match_kernel(KParams P) {
+    match_body<false>(P);
+}
+
+__global__ void __launch_bounds__(64) match_kernel_av(KParams P) { match_body<true>(P); }
+
 int match_blocks_per_cu(bool with_av) {
     int nb = 0;
-    hipError_t e = with_av ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, match_kernel<true>, 64, 0)
-                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, match_kernel<false>, 64, 0);
+    hipError_t e = with_av ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, match_kernel_av, 64, 0)
+                           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, match_kernel, 64, 0);
     if (e != hipSuccess || nb < 1) nb = 8;
     return nb;
 }
 
 hipError_t launch_match(const KParams &P, int grid, bool with_av, hipStream_t s) {
-    if (with_av) hipLaunchKernelGGL(match_kernel<true>, dim3(grid), dim3(64), 0, s, P);
-    else hipLaunchKernelGGL(match_kernel<false>, dim3(grid), dim3(64), 0, s, P);
+    if (with_av) hipLaunchKernelGGL(match_kernel_av, dim3(grid), dim3(64), 0, s, P);
+    else hipLaunchKernelGGL(match_kernel, dim3(grid), dim3(64), 0, s, P);
     return hipGetLastError();
 }
 

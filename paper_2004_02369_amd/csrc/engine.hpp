@@ -12,6 +12,7 @@ enum RunMode : int32_t { kModeCount = 0, kModeExists = 1, kModeEmit = 2 };
 struct KParams {
     const int64_t *rp;
     const int32_t *col;
+    long long ncol;            // entries of col (2m, < 2^31)
     const int32_t *up;         // per vertex: index in its row of the first neighbour above it
     const uint32_t *hub_bits;  // dense adjacency bitmaps of vertices hub_start..n-1 (hub_words each)
     long long hub_words;
