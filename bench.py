@@ -52,11 +52,11 @@ def measured_traffic(kernel_hash):
         return None
 
 
-def cpu_baseline(g, specs, budget_s=15.0):
+def cpu_baseline(g, specs, budget_s=10.0):
     """The oracle's generic matcher on a bounded sample of start vertices of
     the same graph: matches/s = (valid maps / |Aut|) / time, over the six
     induced motifs.  Start vertices are taken in a seeded random order, in
-    blocks of 16, until the time budget is spent."""
+    blocks of 4, until the time budget is spent."""
     import numpy as np
     import oracle
     og = oracle.Graph.from_tuple(g)
@@ -66,7 +66,7 @@ def cpu_baseline(g, specs, budget_s=15.0):
     sample = rng.permutation(n).astype(np.int32)
     spent, matches, used = 0.0, 0.0, 0
     while spent < budget_s and used < n:
-        roots = sample[used:used + 16]
+        roots = sample[used:used + 4]
         t0 = time.perf_counter()
         for s in specs:
             matches += oracle.valid_maps_from(og, s, roots, threads) / oracle.aut(s)
