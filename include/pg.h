@@ -39,6 +39,7 @@ typedef int32_t pg_status;
 #define PG_EDEVICE (-3)       /* HIP runtime error */
 #define PG_EOVERFLOW (-4)     /* a count exceeds 2^64 - 1 */
 #define PG_EUNSUPPORTED (-5)  /* valid request this build does not handle */
+#define PG_ETIMEDOUT (-6)     /* the run's time limit passed; counts are partial (lower bounds) */
 
 typedef struct pg_graph pg_graph;
 typedef struct pg_plan pg_plan;
@@ -58,6 +59,8 @@ typedef struct {
     int32_t labelled;     /* 1 if vertex labels were given */
     int32_t device;       /* HIP device holding the graph */
     const int32_t *perm;  /* host, n entries: perm[rank] = original id; owned by the graph */
+    int32_t resident_waves[2]; /* wavefronts of the matching kernel resident at once on the device
+                                  (patterns without / with anti-vertices): the default grid */
 } pg_graph_info_t;
 
 /* Ingest an undirected graph and make it resident on the GPU (Sec. 5.1,
@@ -165,7 +168,10 @@ typedef struct {
     int32_t grid_waves;    /* persistent wavefronts; 0 = auto (CUs x waves per CU) */
     int32_t chunk;         /* root tasks claimed per atomic; 0 = auto */
     int32_t flags;         /* PG_RUN_* */
-    int32_t reserved[5];   /* must be zero */
+    int32_t time_limit_ms; /* stop every wavefront once this long has passed on the device clock
+                              since the launch's first wavefront started, and return
+                              PG_ETIMEDOUT; 0 = no limit */
+    int32_t reserved[4];   /* must be zero */
 } pg_run_config;
 
 #define PG_RUN_COUNT_BYTES 1  /* also count the merge-model bytes of every set operation */
@@ -212,6 +218,41 @@ pg_status pg_enumerate(pg_graph *g, const pg_plan *plan, int32_t *out, uint64_t 
  * stream; the callback runs on the calling host thread. */
 typedef int (*pg_match_cb)(const int32_t *ids, int32_t k, void *user);
 pg_status pg_match(pg_graph *g, const pg_plan *plan, pg_match_cb cb, void *user, uint64_t *n_matches);
+
+/* ------------------------------------------------------ asynchronous jobs
+ *
+ * For request loops that keep several queries in flight (serving): a job is
+ * one launch of one or more plans (one plan for an existence query) on the
+ * caller's stream, using device memory the caller provides, so admission
+ * can be decided by memory and launches on different streams overlap.  No
+ * call below allocates device memory. */
+
+typedef struct pg_job pg_job;
+
+#define PG_JOB_COUNT 0   /* exact counts of every plan */
+#define PG_JOB_EXISTS 1  /* one plan; stops at the first match (Sec. 5.3) */
+
+/* Device bytes a job of these plans needs (control words, the program trie
+ * and per-wavefront scratch for cfg's grid; cfg NULL = whole-GPU grid). */
+pg_status pg_job_workspace_size(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, int32_t mode,
+                                const pg_run_config *cfg, uint64_t *bytes);
+
+/* Enqueue a job on hip_stream and return without waiting.  workspace:
+ * device memory of at least pg_job_workspace_size() bytes, 256-byte
+ * aligned, owned by the caller and not touched by anything else until
+ * pg_job_finish returns (PG_ENOMEM if too small).  The plans must stay
+ * alive until then.  Jobs on different streams run concurrently. */
+pg_status pg_submit(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, int32_t mode,
+                    const pg_run_config *cfg, void *workspace, uint64_t workspace_bytes, void *hip_stream,
+                    pg_job **out);
+
+/* Non-blocking: done = 1 once the job's kernel has completed. */
+pg_status pg_job_poll(pg_job *job, int32_t *done);
+
+/* Wait for the job, write its counts (host, n_plans entries; for an
+ * existence job counts[0] = 1 if a match exists, else 0) and release the
+ * job handle (not the workspace). */
+pg_status pg_job_finish(pg_job *job, uint64_t *counts, pg_run_stats *stats);
 
 /* Thread-local message for the last error on this thread ("" if none). */
 const char *pg_last_error(void);

@@ -40,11 +40,42 @@ using pg::set_error;
     } while (0)
 
 namespace {
+// Host-side preparation of one launch: the program trie, its upload image
+// and the launch shape.
+struct LaunchPlan {
+    pg::Trie trie;
+    std::vector<char> image;  // nodes | anti-vertex checks | roots
+    size_t a_off = 0, r_off = 0;
+    bool with_av = false;
+    int grid = 0, chunk = 0;
+    long long n_et = 0, n_vt = 0;
+    int enum_levels = 0;
+    long long set_cap = 0, arena_cap = 0;
+    size_t scratch_ints = 0;
+};
+
 inline void dfree(void *p) {
     if (p) (void)hipFree(p);
 }
 inline void edestroy(hipEvent_t e) { (void)hipEventDestroy(e); }
 }  // namespace
+
+struct pg_job {
+    pg_graph *g = nullptr;
+    LaunchPlan L;
+    int32_t n_plans = 0;
+    int32_t mode = 0;
+    unsigned long long *ctl = nullptr;  // in the caller's workspace
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::chrono::steady_clock::time_point t_submit;
+    bool enqueued = false;  // work is on the stream that reads L.image
+    ~pg_job() {
+        if (enqueued) (void)hipStreamSynchronize(s);
+        if (e0) edestroy(e0);
+        if (e1) edestroy(e1);
+    }
+};
 
 struct pg_graph {
     int32_t n = 0;
@@ -52,6 +83,7 @@ struct pg_graph {
     int32_t d_max = 0;
     int32_t device = 0;
     int32_t n_cu = 0;
+    int64_t wall_khz = 0;  // device wall-clock ticks per millisecond
     int32_t blocks_per_cu[2] = {0, 0};  // resident match_kernel wavefronts per CU (without / with anti-vertices)
     bool labelled = false;
     std::vector<int32_t> perm;  // rank -> original id
@@ -74,10 +106,10 @@ struct pg_graph {
     void *trie_buf = nullptr;
     size_t trie_bytes = 0;
     unsigned long long *ctl = nullptr;  // counts[64], cursor, emit_ctr, bytes, flags[2]
-    // cached trie of the last launch
+    // cached launch preparation of the last pg_count / pg_enumerate call
     std::vector<uint64_t> trie_key;
     bool trie_emit = false;
-    pg::Trie trie;
+    LaunchPlan launch;
     bool trie_valid = false;
 
     ~pg_graph() {
@@ -105,8 +137,9 @@ constexpr int kCtlCounts = 0;
 constexpr int kCtlCursor = 64;
 constexpr int kCtlEmit = 65;
 constexpr int kCtlBytes = 66;
-constexpr int kCtlFlags = 67;  // two int32 in one slot
-constexpr int kCtlWords = 68;
+constexpr int kCtlFlags = 67;  // four int32 in two slots: overflow, stop, timed out, unused
+constexpr int kCtlStart = 69;  // device wall clock at the first wavefront's start
+constexpr int kCtlWords = 70;
 
 struct DeviceGuard {
     int prev = -1;
@@ -276,6 +309,10 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         hipDeviceProp_t prop;
         PG_HIP(hipGetDeviceProperties(&prop, dev));
         g->n_cu = prop.multiProcessorCount;
+        int khz = 0;
+        PG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+        if (khz <= 0) { set_error("device reports no wall-clock rate"); return PG_EDEVICE; }
+        g->wall_khz = khz;
         g->blocks_per_cu[0] = pg::match_blocks_per_cu(false);
         g->blocks_per_cu[1] = pg::match_blocks_per_cu(true);
         pg_status st;
@@ -328,6 +365,8 @@ pg_status pg_graph_info(const pg_graph *g, pg_graph_info_t *out) {
     out->labelled = g->labelled ? 1 : 0;
     out->device = g->device;
     out->perm = g->perm.data();
+    out->resident_waves[0] = g->n_cu * g->blocks_per_cu[0];
+    out->resident_waves[1] = g->n_cu * g->blocks_per_cu[1];
     return PG_OK;
 }
 
@@ -418,83 +457,56 @@ struct LaunchArgs {
     uint64_t cap = 0;
 };
 
-pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts, const pg_run_config *cfg,
-              pg_run_stats *stats, void *hip_stream, const LaunchArgs &la, uint64_t *emitted) {
-    auto t_start = std::chrono::steady_clock::now();
+pg_status check_args(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, const pg_run_config *cfg) {
     if (!g) { set_error("NULL graph"); return PG_EINVAL; }
     if (n_plans < 1 || n_plans > pg::kMaxPlansPerLaunch) { set_error("n_plans must be in [1, 64]"); return PG_EINVAL; }
     if (!plans) { set_error("plans is NULL"); return PG_EINVAL; }
     for (int i = 0; i < n_plans; i++)
         if (!plans[i]) { set_error("a plan is NULL"); return PG_EINVAL; }
     if (cfg) {
-        if (cfg->grid_waves < 0 || cfg->chunk < 0) { set_error("negative launch knob"); return PG_EINVAL; }
-        for (int i = 0; i < 5; i++)
+        if (cfg->grid_waves < 0 || cfg->chunk < 0 || cfg->time_limit_ms < 0) {
+            set_error("negative launch knob");
+            return PG_EINVAL;
+        }
+        for (int i = 0; i < 4; i++)
             if (cfg->reserved[i]) { set_error("pg_run_config.reserved must be zero"); return PG_EINVAL; }
     }
-    std::lock_guard<std::mutex> lock(g->mu);
-    DeviceGuard guard(g->device);
-    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
-    const bool emit = la.mode == pg::kModeEmit;
+    return PG_OK;
+}
 
-    // program trie (cached for a repeated plan list)
-    std::vector<uint64_t> key;
-    for (int i = 0; i < n_plans; i++) key.push_back(plans[i]->uid);
-    if (!g->trie_valid || g->trie_key != key || g->trie_emit != emit) {
-        std::vector<const pg::PlanImpl *> impls;
-        for (int i = 0; i < n_plans; i++) impls.push_back(&plans[i]->impl);
-        g->trie = pg::build_trie(impls, emit);
-        g->trie_key = key;
-        g->trie_emit = emit;
-        g->trie_valid = true;
-    }
-    const pg::Trie &T = g->trie;
+// shape of a launch for a built trie
+void shape(const pg_graph *g, const pg_run_config *cfg, LaunchPlan &L) {
+    const pg::Trie &T = L.trie;
+    L.with_av = !T.avs.empty();
+    // persistent grid: exactly the wavefronts that can be resident at once
+    L.grid = cfg && cfg->grid_waves ? cfg->grid_waves : g->n_cu * g->blocks_per_cu[L.with_av ? 1 : 0];
+    L.n_et = T.has_edge_root ? (long long)g->m : 0;
+    L.n_vt = T.has_vertex_root ? (long long)g->n : 0;
+    L.chunk = cfg && cfg->chunk ? cfg->chunk : 64;
+    // scratch: one set per enumeration level (levels 2 .. max_level-2) plus
+    // the arena of batched expansions
+    L.enum_levels = std::max(0, T.max_level - 3);
+    L.set_cap = std::max<long long>(1, g->d_max);
+    L.arena_cap = L.enum_levels ? kArenaInts : 0;
+    L.scratch_ints = (size_t)L.grid * ((size_t)L.enum_levels * (size_t)L.set_cap + (size_t)L.arena_cap);
+    const size_t nb = T.nodes.size() * sizeof(pg::Node), ab = T.avs.size() * sizeof(pg::AVCheck),
+                 rb = T.roots.size() * sizeof(int32_t);
+    L.a_off = (nb + 15) & ~size_t(15);
+    L.r_off = (L.a_off + ab + 15) & ~size_t(15);
+    L.image.assign(L.r_off + rb + 64, 0);
+    std::memcpy(L.image.data(), T.nodes.data(), nb);
+    std::memcpy(L.image.data() + L.a_off, T.avs.data(), ab);
+    std::memcpy(L.image.data() + L.r_off, T.roots.data(), rb);
+}
+
+pg_status check_trie(const pg::Trie &T) {
     if (T.max_level > pg::kMaxLevels) { set_error("plan too deep"); return PG_EUNSUPPORTED; }
     if (!T.consistent) { set_error("internal: program trie lost a program"); return PG_EUNSUPPORTED; }
+    return PG_OK;
+}
 
-    // upload the trie: nodes | avs | roots
-    size_t nb = T.nodes.size() * sizeof(pg::Node), ab = T.avs.size() * sizeof(pg::AVCheck),
-           rb = T.roots.size() * sizeof(int32_t);
-    size_t need = nb + ab + rb + 64;
-    if (need > g->trie_bytes) {
-        dfree(g->trie_buf);
-        g->trie_buf = nullptr;
-        g->trie_bytes = 0;
-        if (hipMalloc(&g->trie_buf, need) != hipSuccess) { set_error("hipMalloc trie"); return PG_ENOMEM; }
-        g->trie_bytes = need;
-    }
-    std::vector<char> host(need, 0);
-    std::memcpy(host.data(), T.nodes.data(), nb);
-    size_t a_off = (nb + 15) & ~size_t(15);
-    std::memcpy(host.data() + a_off, T.avs.data(), ab);
-    size_t r_off = (a_off + ab + 15) & ~size_t(15);
-    std::memcpy(host.data() + r_off, T.roots.data(), rb);
-    PG_HIP(hipMemcpyAsync(g->trie_buf, host.data(), need, hipMemcpyHostToDevice, s));
-
-    // launch shape
-    // persistent grid: exactly the wavefronts that can be resident at once
-    const bool with_av = !T.avs.empty();
-    int grid = cfg && cfg->grid_waves ? cfg->grid_waves : g->n_cu * g->blocks_per_cu[with_av ? 1 : 0];
-    const long long n_et = T.has_edge_root ? (long long)g->m : 0;
-    const long long n_vt = T.has_vertex_root ? (long long)g->n : 0;
-    int chunk = cfg && cfg->chunk ? cfg->chunk : 64;
-    // scratch: one set per enumeration level (levels 2 .. max_level-2)
-    const int enum_levels = std::max(0, T.max_level - 3);
-    const long long set_cap = std::max<long long>(1, g->d_max);
-    // level-2 arena for task batches (candidates of up to 64 edge tasks)
-    const long long arena_cap = enum_levels ? kArenaInts : 0;
-    const size_t need_ints = (size_t)grid * ((size_t)enum_levels * (size_t)set_cap + (size_t)arena_cap);
-    if (need_ints > g->scratch_ints) {
-        dfree(g->scratch);
-        g->scratch = nullptr;
-        g->scratch_ints = 0;
-        if (hipMalloc(reinterpret_cast<void **>(&g->scratch), need_ints * sizeof(int32_t)) != hipSuccess) {
-            set_error("hipMalloc scratch");
-            return PG_ENOMEM;
-        }
-        g->scratch_ints = need_ints;
-    }
-    PG_HIP(hipMemsetAsync(g->ctl, 0, kCtlWords * sizeof(unsigned long long), s));
-
+pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev, unsigned long long *ctl,
+                   int32_t *scratch, const LaunchArgs &la, int32_t n_plans, const pg_run_config *cfg) {
     pg::KParams P;
     std::memset(&P, 0, sizeof(P));
     P.rp = g->rp;
@@ -508,34 +520,104 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     P.perm = g->dperm;
     P.tsrc = g->tsrc;
     P.tdst = g->tdst;
-    P.nodes = reinterpret_cast<const pg::Node *>(g->trie_buf);
-    P.avs = reinterpret_cast<const pg::AVCheck *>(static_cast<char *>(g->trie_buf) + a_off);
-    P.roots = reinterpret_cast<const int32_t *>(static_cast<char *>(g->trie_buf) + r_off);
-    P.cursor = g->ctl + kCtlCursor;
-    P.counts = g->ctl + kCtlCounts;
-    P.flags = reinterpret_cast<int32_t *>(g->ctl + kCtlFlags);
-    P.emit_ctr = g->ctl + kCtlEmit;
+    P.nodes = reinterpret_cast<const pg::Node *>(trie_dev);
+    P.avs = reinterpret_cast<const pg::AVCheck *>(static_cast<const char *>(trie_dev) + L.a_off);
+    P.roots = reinterpret_cast<const int32_t *>(static_cast<const char *>(trie_dev) + L.r_off);
+    P.cursor = ctl + kCtlCursor;
+    P.counts = ctl + kCtlCounts;
+    P.flags = reinterpret_cast<int32_t *>(ctl + kCtlFlags);
+    P.emit_ctr = ctl + kCtlEmit;
     P.out = la.out;
-    P.bytes_ctr = g->ctl + kCtlBytes;
-    P.scratch = enum_levels ? g->scratch : nullptr;
-    P.wave_stride = (long long)enum_levels * set_cap + arena_cap;
-    P.set_cap = set_cap;
-    P.arena_cap = arena_cap;
-    P.n_etasks = n_et;
-    P.n_vtasks = n_vt;
+    P.bytes_ctr = ctl + kCtlBytes;
+    P.t_start = ctl + kCtlStart;
+    P.time_budget = cfg && cfg->time_limit_ms ? (long long)cfg->time_limit_ms * g->wall_khz : 0;
+    P.scratch = L.enum_levels ? scratch : nullptr;
+    P.wave_stride = (long long)L.enum_levels * L.set_cap + L.arena_cap;
+    P.set_cap = L.set_cap;
+    P.arena_cap = L.arena_cap;
+    P.n_etasks = L.n_et;
+    P.n_vtasks = L.n_vt;
     P.cap = la.cap;
     P.n = g->n;
-    P.n_roots = (int32_t)T.roots.size();
-    P.chunk = chunk;
+    P.n_roots = (int32_t)L.trie.roots.size();
+    P.chunk = L.chunk;
     P.n_plans = n_plans;
     P.mode = la.mode;
     P.run_flags = cfg ? cfg->flags : 0;
+    return P;
+}
+
+pg_status read_ctl(const unsigned long long *ctl, int32_t n_plans, uint64_t *counts, uint64_t *emitted) {
+    const int32_t *flags = reinterpret_cast<const int32_t *>(ctl + kCtlFlags);
+    if (counts)
+        for (int i = 0; i < n_plans; i++) counts[i] = ctl[kCtlCounts + i];
+    if (emitted) *emitted = ctl[kCtlEmit];
+    if (flags[2]) {
+        set_error("time limit reached; counts are partial");
+        return PG_ETIMEDOUT;
+    }
+    if (flags[0]) {
+        set_error("a count exceeds 2^64 - 1");
+        return PG_EOVERFLOW;
+    }
+    return PG_OK;
+}
+
+pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts, const pg_run_config *cfg,
+              pg_run_stats *stats, void *hip_stream, const LaunchArgs &la, uint64_t *emitted) {
+    auto t_start = std::chrono::steady_clock::now();
+    pg_status st = check_args(g, plans, n_plans, cfg);
+    if (st) return st;
+    std::lock_guard<std::mutex> lock(g->mu);
+    DeviceGuard guard(g->device);
+    hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+    const bool emit = la.mode == pg::kModeEmit;
+
+    // program trie (cached for a repeated plan list)
+    std::vector<uint64_t> key;
+    for (int i = 0; i < n_plans; i++) key.push_back(plans[i]->uid);
+    if (!g->trie_valid || g->trie_key != key || g->trie_emit != emit) {
+        std::vector<const pg::PlanImpl *> impls;
+        for (int i = 0; i < n_plans; i++) impls.push_back(&plans[i]->impl);
+        g->launch.trie = pg::build_trie(impls, emit);
+        if ((st = check_trie(g->launch.trie))) {
+            g->trie_valid = false;
+            return st;
+        }
+        shape(g, cfg, g->launch);
+        g->trie_key = key;
+        g->trie_emit = emit;
+        g->trie_valid = true;
+    }
+    LaunchPlan &L = g->launch;
+    shape(g, cfg, L);  // the knobs may differ between calls
+
+    if (L.image.size() > g->trie_bytes) {
+        dfree(g->trie_buf);
+        g->trie_buf = nullptr;
+        g->trie_bytes = 0;
+        if (hipMalloc(&g->trie_buf, L.image.size()) != hipSuccess) { set_error("hipMalloc trie"); return PG_ENOMEM; }
+        g->trie_bytes = L.image.size();
+    }
+    PG_HIP(hipMemcpyAsync(g->trie_buf, L.image.data(), L.image.size(), hipMemcpyHostToDevice, s));
+    if (L.scratch_ints > g->scratch_ints) {
+        dfree(g->scratch);
+        g->scratch = nullptr;
+        g->scratch_ints = 0;
+        if (hipMalloc(reinterpret_cast<void **>(&g->scratch), L.scratch_ints * sizeof(int32_t)) != hipSuccess) {
+            set_error("hipMalloc scratch");
+            return PG_ENOMEM;
+        }
+        g->scratch_ints = L.scratch_ints;
+    }
+    PG_HIP(hipMemsetAsync(g->ctl, 0, kCtlWords * sizeof(unsigned long long), s));
+    const pg::KParams P = params(g, L, g->trie_buf, g->ctl, g->scratch, la, n_plans, cfg);
 
     hipEvent_t e0, e1;
     PG_HIP(hipEventCreate(&e0));
     PG_HIP(hipEventCreate(&e1));
     PG_HIP(hipEventRecord(e0, s));
-    hipError_t le = pg::launch_match(P, grid, with_av, s);
+    hipError_t le = pg::launch_match(P, L.grid, L.with_av, s);
     if (le != hipSuccess) {
         edestroy(e0);
         edestroy(e1);
@@ -550,24 +632,25 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     PG_HIP(hipEventElapsedTime(&ms, e0, e1));
     edestroy(e0);
     edestroy(e1);
-    const int32_t *flags = reinterpret_cast<const int32_t *>(ctl + kCtlFlags);
-    if (counts)
-        for (int i = 0; i < n_plans; i++) counts[i] = ctl[kCtlCounts + i];
-    if (emitted) *emitted = ctl[kCtlEmit];
     if (stats) {
         stats->kernel_ms = ms;
         stats->total_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         stats->logical_bytes = ctl[kCtlBytes];
-        stats->root_tasks = (uint64_t)(n_et + n_vt);
-        stats->grid_waves = grid;
-        stats->chunk = chunk;
+        stats->root_tasks = (uint64_t)(L.n_et + L.n_vt);
+        stats->grid_waves = L.grid;
+        stats->chunk = L.chunk;
     }
-    if (flags[0]) {
-        set_error("a count exceeds 2^64 - 1");
-        return PG_EOVERFLOW;
-    }
-    return PG_OK;
+    return read_ctl(ctl, n_plans, counts, emitted);
+}
+
+constexpr size_t kWsAlign = 256;
+inline size_t align_up(size_t x) { return (x + kWsAlign - 1) & ~(kWsAlign - 1); }
+
+// workspace layout of an asynchronous job: control words | trie image | scratch
+size_t workspace_bytes(const LaunchPlan &L) {
+    return align_up(kCtlWords * sizeof(unsigned long long)) + align_up(L.image.size()) +
+           L.scratch_ints * sizeof(int32_t);
 }
 
 }  // namespace
@@ -660,6 +743,138 @@ pg_status pg_match(pg_graph *g, const pg_plan *plan, pg_match_cb cb, void *user,
         if (cb(h.data() + i * (uint64_t)k, k, user)) return PG_STOPPED;
     }
     return PG_OK;
+}
+
+
+// ----------------------------------------------------------- asynchronous jobs
+
+static pg_status prepare_job(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, int32_t mode,
+                             const pg_run_config *cfg, LaunchPlan *L) {
+    pg_status st = check_args(g, plans, n_plans, cfg);
+    if (st) return st;
+    if (mode != PG_JOB_COUNT && mode != PG_JOB_EXISTS) { set_error("unknown job mode"); return PG_EINVAL; }
+    if (mode == PG_JOB_EXISTS && n_plans != 1) { set_error("an existence job takes one plan"); return PG_EINVAL; }
+    std::vector<const pg::PlanImpl *> impls;
+    for (int i = 0; i < n_plans; i++) impls.push_back(&plans[i]->impl);
+    L->trie = pg::build_trie(impls, false);
+    if ((st = check_trie(L->trie))) return st;
+    pg_run_config c;
+    std::memset(&c, 0, sizeof(c));
+    if (cfg) c = *cfg;
+    if (mode == PG_JOB_EXISTS && !c.chunk) c.chunk = 1;  // poll the stop flag often
+    shape(g, &c, *L);
+    return PG_OK;
+}
+
+pg_status pg_job_workspace_size(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, int32_t mode,
+                                const pg_run_config *cfg, uint64_t *bytes) {
+    if (!bytes) { set_error("bytes is NULL"); return PG_EINVAL; }
+    try {
+        LaunchPlan L;
+        pg_status st = prepare_job(g, plans, n_plans, mode, cfg, &L);
+        if (st) return st;
+        *bytes = workspace_bytes(L);
+        return PG_OK;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    }
+}
+
+pg_status pg_submit(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, int32_t mode,
+                    const pg_run_config *cfg, void *workspace, uint64_t workspace_bytes_, void *hip_stream,
+                    pg_job **out) {
+    if (!out) { set_error("out is NULL"); return PG_EINVAL; }
+    *out = nullptr;
+    try {
+        std::unique_ptr<pg_job> j(new pg_job());
+        pg_status st = prepare_job(g, plans, n_plans, mode, cfg, &j->L);
+        if (st) return st;
+        const uint64_t need = workspace_bytes(j->L);
+        if (!workspace || workspace_bytes_ < need) {
+            set_error("workspace too small: need " + std::to_string(need) + " bytes");
+            return PG_ENOMEM;
+        }
+        if (reinterpret_cast<uintptr_t>(workspace) % kWsAlign) {
+            set_error("workspace must be 256-byte aligned");
+            return PG_EINVAL;
+        }
+        DeviceGuard guard(g->device);
+        j->g = g;
+        j->n_plans = n_plans;
+        j->mode = mode;
+        j->s = reinterpret_cast<hipStream_t>(hip_stream);
+        j->t_submit = std::chrono::steady_clock::now();
+        char *base = static_cast<char *>(workspace);
+        j->ctl = reinterpret_cast<unsigned long long *>(base);
+        char *trie = base + align_up(kCtlWords * sizeof(unsigned long long));
+        int32_t *scratch = reinterpret_cast<int32_t *>(trie + align_up(j->L.image.size()));
+        j->enqueued = true;
+        PG_HIP(hipMemcpyAsync(trie, j->L.image.data(), j->L.image.size(), hipMemcpyHostToDevice, j->s));
+        PG_HIP(hipMemsetAsync(j->ctl, 0, kCtlWords * sizeof(unsigned long long), j->s));
+        LaunchArgs la;
+        la.mode = mode == PG_JOB_EXISTS ? pg::kModeExists : pg::kModeCount;
+        const pg::KParams P = params(g, j->L, trie, j->ctl, scratch, la, n_plans, cfg);
+        PG_HIP(hipEventCreate(&j->e0));
+        PG_HIP(hipEventCreate(&j->e1));
+        PG_HIP(hipEventRecord(j->e0, j->s));
+        hipError_t le = pg::launch_match(P, j->L.grid, j->L.with_av, j->s);
+        if (le != hipSuccess) {
+            set_error(std::string("kernel launch: ") + hipGetErrorString(le));
+            return PG_EDEVICE;
+        }
+        PG_HIP(hipEventRecord(j->e1, j->s));
+        *out = j.release();
+        return PG_OK;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    }
+}
+
+pg_status pg_job_poll(pg_job *j, int32_t *done) {
+    if (!j || !done) { set_error("NULL argument"); return PG_EINVAL; }
+    DeviceGuard guard(j->g->device);
+    hipError_t e = hipEventQuery(j->e1);
+    if (e == hipSuccess) *done = 1;
+    else if (e == hipErrorNotReady) *done = 0;
+    else {
+        set_error(std::string("hipEventQuery: ") + hipGetErrorString(e));
+        return PG_EDEVICE;
+    }
+    return PG_OK;
+}
+
+pg_status pg_job_finish(pg_job *j, uint64_t *counts, pg_run_stats *stats) {
+    if (!j) { set_error("NULL job"); return PG_EINVAL; }
+    std::unique_ptr<pg_job> own(j);
+    DeviceGuard guard(j->g->device);
+    unsigned long long ctl[kCtlWords];
+    PG_HIP(hipMemcpyAsync(ctl, j->ctl, sizeof(ctl), hipMemcpyDeviceToHost, j->s));
+    PG_HIP(hipStreamSynchronize(j->s));
+    j->enqueued = false;
+    float ms = 0.f;
+    PG_HIP(hipEventElapsedTime(&ms, j->e0, j->e1));
+    if (stats) {
+        stats->kernel_ms = ms;
+        stats->total_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - j->t_submit).count();
+        stats->logical_bytes = ctl[kCtlBytes];
+        stats->root_tasks = (uint64_t)(j->L.n_et + j->L.n_vt);
+        stats->grid_waves = j->L.grid;
+        stats->chunk = j->L.chunk;
+    }
+    if (j->mode == PG_JOB_EXISTS) {
+        // partial sums of an early-stopped search may wrap; only > 0 matters
+        const int32_t *flags = reinterpret_cast<const int32_t *>(ctl + kCtlFlags);
+        if (flags[2] && ctl[kCtlCounts] == 0) {
+            set_error("time limit reached before a match was found");
+            return PG_ETIMEDOUT;
+        }
+        if (counts) counts[0] = ctl[kCtlCounts] > 0 ? 1 : 0;
+        return PG_OK;
+    }
+    return read_ctl(ctl, j->n_plans, counts, nullptr);
 }
 
 }  // extern "C"

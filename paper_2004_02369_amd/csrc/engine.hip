@@ -81,6 +81,7 @@ struct Lds {
     int32_t seg_own[kSeg];
     int32_t stop;
     unsigned long long bytes;
+    unsigned long long t_start;
 };
 
 struct RowRef {
@@ -659,6 +660,7 @@ struct Ctx {
         amode = 0;
         vl0 = x;
         for (int32_t s = 0; s < len; s += kP) {
+            if (stopped()) break;
             const int np = min(kP, len - s);
             if (lane < np) {
                 const int32_t v = S[s + lane];
@@ -692,11 +694,18 @@ struct Ctx {
         wsync();
     }
 
+    // early exit: another wavefront found a match (existence) or the
+    // launch's time limit has passed (then every wavefront is told to stop)
     __device__ __forceinline__ bool stopped() {
-        if (P.mode != kModeExists) return false;
+        if (P.mode != kModeExists && !P.time_budget) return false;
         if (lane == 0) {
-            int f = __atomic_load_n(P.flags + 1, __ATOMIC_RELAXED);
-            if (f) L.stop = 1;
+            if (__atomic_load_n(P.flags + 1, __ATOMIC_RELAXED)) {
+                L.stop = 1;
+            } else if (P.time_budget && (long long)(wall_clock64() - L.t_start) > P.time_budget) {
+                L.stop = 1;
+                atomicOr(P.flags + 2, 1);
+                atomicOr(P.flags + 1, 1);
+            }
         }
         wsync();
         return L.stop != 0;
@@ -773,6 +782,7 @@ struct Ctx {
         const unsigned long long bigmask = __ballot(big);
         unsigned long long remaining = __ballot(ok && !big);
         while (remaining) {
+            if (stopped()) break;
             // parent slots as the materialisation pass reads them (a previous
             // round's count phase reused these arrays)
             L.pdrv[lane] = (int8_t)drv;
@@ -883,6 +893,7 @@ struct Ctx {
             const int sp0 = plev0, sp1 = plev1;
             for (int l = 0; l < np; l++) {
                 if (!(bigmask >> l & 1ull)) continue;
+                if (stopped()) break;
                 if (sp0 >= 0) set_level(sp0, L.tu[l], L.tidx[l]);
                 if (sp1 >= 0) set_level(sp1, L.tv[l], 0);
                 plev0 = plev1 = -1;
@@ -1097,6 +1108,12 @@ __device__ __forceinline__ void match_body(const KParams P) {
     if (lane == 0) {
         L.stop = 0;
         L.bytes = 0;
+        L.t_start = 0;
+        if (P.time_budget) {
+            const unsigned long long now = wall_clock64();
+            const unsigned long long old = atomicCAS(P.t_start, 0ull, now);
+            L.t_start = old ? old : now;
+        }
     }
     wsync();
     const long long total_tasks = P.n_etasks + P.n_vtasks;

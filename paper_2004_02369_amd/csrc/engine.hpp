@@ -26,7 +26,8 @@ struct KParams {
     const int32_t *roots;
     unsigned long long *cursor;
     unsigned long long *counts;
-    int32_t *flags;            // [0] overflow, [1] stop
+    int32_t *flags;            // [0] overflow, [1] stop, [2] time limit reached
+    unsigned long long *t_start; // device wall clock when the first wavefront started (0 = not yet)
     unsigned long long *emit_ctr;
     int32_t *out;
     unsigned long long *bytes_ctr;
@@ -37,6 +38,7 @@ struct KParams {
     long long n_etasks;
     long long n_vtasks;
     unsigned long long cap;    // emit capacity (rows)
+    long long time_budget;     // wall-clock ticks from the first wavefront's start; 0 = unlimited
     int32_t n;
     int32_t n_roots;
     int32_t chunk;

@@ -238,6 +238,8 @@ WORKLOADS = {
     "chunglu_100k_1m": dict(kind="cl", n=100_000, m=1_000_000, gamma=2.1, w_max=5000.0, seed=20002),
     # R-MAT a=.57 b=c=.19, edge factor 16 (16M edges stand in for Patents' edge count)
     "rmat20_16m": dict(kind="rmat", scale=20, m=16 * (1 << 20), seed=20003),
+    # the serving graph: 4M vertices, 64M edges (CSR larger than the last-level cache)
+    "rmat22_64m": dict(kind="rmat", scale=22, m=16 * (1 << 22), seed=20008),
     "rmat16_1m": dict(kind="rmat", scale=16, m=16 * (1 << 16), seed=20004),
     "rmat14_256k": dict(kind="rmat", scale=14, m=16 * (1 << 14), seed=20005),
     "rmat12_64k": dict(kind="rmat", scale=12, m=16 * (1 << 12), seed=20006),

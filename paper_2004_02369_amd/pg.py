@@ -20,13 +20,14 @@ LIB_PATH = os.path.join(HERE, "libpg.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "pg.h")
 
 PG_OK, PG_STOPPED = 0, 1
-PG_EINVAL, PG_ENOMEM, PG_EDEVICE, PG_EOVERFLOW, PG_EUNSUPPORTED = -1, -2, -3, -4, -5
+PG_EINVAL, PG_ENOMEM, PG_EDEVICE, PG_EOVERFLOW, PG_EUNSUPPORTED, PG_ETIMEDOUT = -1, -2, -3, -4, -5, -6
 PG_EDGE, PG_ANTI_EDGE = 0, 1
 PG_PLAN_AUTO, PG_PLAN_LINEAR_EXT, PG_PLAN_PARTIAL_ORDER = 0, 1, 2
 PG_RUN_COUNT_BYTES, PG_RUN_NO_MODE_B, PG_RUN_NO_TASK_BATCH = 1, 2, 4
+PG_JOB_COUNT, PG_JOB_EXISTS = 0, 1
 
 _STATUS = {PG_EINVAL: "EINVAL", PG_ENOMEM: "ENOMEM", PG_EDEVICE: "EDEVICE", PG_EOVERFLOW: "EOVERFLOW",
-           PG_EUNSUPPORTED: "EUNSUPPORTED"}
+           PG_EUNSUPPORTED: "EUNSUPPORTED", PG_ETIMEDOUT: "ETIMEDOUT"}
 
 
 class PGError(RuntimeError):
@@ -42,7 +43,7 @@ class pg_options(ctypes.Structure):
 class pg_graph_info_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("d_max", ctypes.c_int32), ("m", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("labelled", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("perm", ctypes.POINTER(ctypes.c_int32))]
+                ("perm", ctypes.POINTER(ctypes.c_int32)), ("resident_waves", ctypes.c_int32 * 2)]
 
 
 class pg_edge(ctypes.Structure):
@@ -70,7 +71,7 @@ class pg_plan_info_t(ctypes.Structure):
 
 class pg_run_config(ctypes.Structure):
     _fields_ = [("grid_waves", ctypes.c_int32), ("chunk", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("time_limit_ms", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class pg_run_stats(ctypes.Structure):
@@ -83,7 +84,8 @@ MATCH_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes
 
 EXPORTS = ["pg_load_graph", "pg_graph_info", "pg_graph_csr", "pg_free_graph", "pg_plan_pattern",
            "pg_plan_pattern_ex", "pg_plan_info", "pg_free_plan", "pg_plan_programs", "pg_count", "pg_count_ex",
-           "pg_exists", "pg_enumerate", "pg_match", "pg_last_error"]
+           "pg_exists", "pg_enumerate", "pg_match", "pg_job_workspace_size", "pg_submit", "pg_job_poll",
+           "pg_job_finish", "pg_last_error"]
 
 _lib = None
 
@@ -115,6 +117,12 @@ def lib():
     L.pg_exists.argtypes = [vp, vp, ctypes.POINTER(i32), vp]
     L.pg_enumerate.argtypes = [vp, vp, vp, u64, ctypes.POINTER(u64), vp]
     L.pg_match.argtypes = [vp, vp, MATCH_CB, vp, ctypes.POINTER(u64)]
+    L.pg_job_workspace_size.argtypes = [vp, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(pg_run_config),
+                                        ctypes.POINTER(u64)]
+    L.pg_submit.argtypes = [vp, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(pg_run_config), vp, u64, vp,
+                            ctypes.POINTER(vp)]
+    L.pg_job_poll.argtypes = [vp, ctypes.POINTER(i32)]
+    L.pg_job_finish.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(pg_run_stats)]
     L.pg_last_error.argtypes = []
     L.pg_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -149,6 +157,7 @@ class Graph:
         self.device_bytes = info.device_bytes
         self.device = info.device
         self.perm = np.ctypeslib.as_array(info.perm, shape=(info.n,)).copy()
+        self.resident_waves = (int(info.resident_waves[0]), int(info.resident_waves[1]))
 
     def csr(self):
         rp = np.zeros(self.n + 1, dtype=np.int64)
@@ -270,17 +279,22 @@ def plan_pattern(spec, mode: int = PG_PLAN_AUTO) -> Plan:
 
 # --------------------------------------------------------------- counting
 
-def count_ex(graph: Graph, plans, stream=None, grid_waves=0, chunk=0, flags=0):
+def count_ex(graph: Graph, plans, stream=None, grid_waves=0, chunk=0, flags=0, time_limit_ms=0):
+    """Counts and stats of one launch.  With a time limit, a run that hits it
+    raises PGError with status PG_ETIMEDOUT."""
     plans = list(plans)
     arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
     out = (ctypes.c_uint64 * len(plans))()
-    cfg = pg_run_config(grid_waves=grid_waves, chunk=chunk, flags=flags)
+    cfg = pg_run_config(grid_waves=grid_waves, chunk=chunk, flags=flags, time_limit_ms=time_limit_ms)
     st = pg_run_stats()
     _check(lib().pg_count_ex(graph._h, arr, len(plans), out, ctypes.byref(cfg), ctypes.byref(st),
                              _stream_ptr(stream)))
-    stats = {"kernel_ms": st.kernel_ms, "total_ms": st.total_ms, "logical_bytes": st.logical_bytes,
-             "root_tasks": st.root_tasks, "grid_waves": st.grid_waves, "chunk": st.chunk}
-    return [int(x) for x in out], stats
+    return [int(x) for x in out], _stats(st)
+
+
+def _stats(st):
+    return {"kernel_ms": st.kernel_ms, "total_ms": st.total_ms, "logical_bytes": st.logical_bytes,
+            "root_tasks": st.root_tasks, "grid_waves": st.grid_waves, "chunk": st.chunk}
 
 
 def count(graph: Graph, plans, stream=None, **kw):
@@ -320,3 +334,57 @@ def match(graph: Graph, plan: Plan, fn) -> tuple[int, bool]:
     n = ctypes.c_uint64()
     st = _check(lib().pg_match(graph._h, plan._h, c, None, ctypes.byref(n)))
     return int(n.value), st == PG_STOPPED
+
+
+# ------------------------------------------------------- asynchronous jobs
+
+def job_workspace_size(graph: Graph, plans, mode=PG_JOB_COUNT, grid_waves=0, chunk=0, flags=0) -> int:
+    plans = list(plans)
+    arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    cfg = pg_run_config(grid_waves=grid_waves, chunk=chunk, flags=flags)  # the time limit does not change it
+    b = ctypes.c_uint64()
+    _check(lib().pg_job_workspace_size(graph._h, arr, len(plans), mode, ctypes.byref(cfg), ctypes.byref(b)))
+    return int(b.value)
+
+
+class Job:
+    """One launch in flight (pg_submit).  Keeps its plans and workspace alive
+    until finish()."""
+
+    def __init__(self, handle, plans, workspace, mode):
+        self._h = ctypes.c_void_p(handle)
+        self.plans = plans
+        self.workspace = workspace
+        self.mode = mode
+
+    def done(self) -> bool:
+        d = ctypes.c_int32()
+        _check(lib().pg_job_poll(self._h, ctypes.byref(d)))
+        return bool(d.value)
+
+    def finish(self):
+        """Counts (list) or, for an existence job, a bool; plus stats."""
+        if self._h is None:
+            raise PGError(PG_EINVAL, "job already finished")
+        out = (ctypes.c_uint64 * len(self.plans))()
+        st = pg_run_stats()
+        h, self._h = self._h, None
+        _check(lib().pg_job_finish(h, out, ctypes.byref(st)))
+        self.workspace = None
+        res = [int(x) for x in out]
+        return (bool(res[0]) if self.mode == PG_JOB_EXISTS else res), _stats(st)
+
+
+def submit(graph: Graph, plans, workspace, stream, mode=PG_JOB_COUNT, grid_waves=0, chunk=0, flags=0,
+           time_limit_ms=0) -> Job:
+    """Enqueue one launch on `stream` (a torch.cuda.Stream or raw handle).
+    `workspace` is a device uint8 torch tensor of at least
+    job_workspace_size() bytes with a 256-byte aligned data pointer."""
+    plans = list(plans)
+    arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    cfg = pg_run_config(grid_waves=grid_waves, chunk=chunk, flags=flags, time_limit_ms=time_limit_ms)
+    h = ctypes.c_void_p()
+    _check(lib().pg_submit(graph._h, arr, len(plans), mode, ctypes.byref(cfg),
+                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
+                           _stream_ptr(stream), ctypes.byref(h)))
+    return Job(h.value, plans, workspace, mode)

@@ -1,0 +1,506 @@
+"""Serving many pattern queries over one resident graph.
+
+Requests arrive over time (count or existence queries).  The loop admits
+them while launch slots and workspace memory are free:
+
+* every admitted batch is one asynchronous launch (``pg.submit``) on a stream
+  of its own, with a grid of ``resident waves / slots`` wavefronts, so up to
+  ``slots`` launches run side by side;
+* count requests waiting in the queue are merged into one launch
+  (continuous batching): their plans share one root frontier (Sec. 5.4),
+  identical plans are counted once, up to 64 plans per launch;
+* an existence query runs in a launch of its own (shared only with repeats
+  of the same query), with its own stop flag, and ends at the first match
+  (Sec. 5.3);
+* a launch is admitted only when its workspace (control words, program trie,
+  per-wavefront scratch) fits in what is left of a fixed device pool; the
+  pool is carved first-fit, never grown.
+
+Everything here is host logic; the matching runs in libpg.
+
+    python -m paper_2004_02369_amd.serve --workload rmat22_64m --qps 50,100,200,500
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import itertools
+import json
+import math
+import sys
+import time
+from dataclasses import dataclass, field
+
+ALIGN = 256
+MAX_PLANS = 64
+
+
+# ------------------------------------------------------------------ pool
+
+class Pool:
+    """First-fit allocator of byte ranges in [0, size), ALIGN-aligned."""
+
+    def __init__(self, size: int):
+        self.size = size - size % ALIGN
+        self.free_list = [(0, self.size)]  # sorted (offset, length)
+        self.live = {}
+
+    @property
+    def used(self) -> int:
+        return sum(self.live.values())
+
+    def largest_free(self) -> int:
+        return max((n for _, n in self.free_list), default=0)
+
+    def alloc(self, nbytes: int):
+        n = max(ALIGN, -(-nbytes // ALIGN) * ALIGN)
+        for i, (off, length) in enumerate(self.free_list):
+            if length >= n:
+                if length == n:
+                    del self.free_list[i]
+                else:
+                    self.free_list[i] = (off + n, length - n)
+                self.live[off] = n
+                return off
+        return None
+
+    def free(self, off: int):
+        n = self.live.pop(off)
+        fl = self.free_list
+        fl.append((off, n))
+        fl.sort()
+        merged = []
+        for o, ln in fl:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + ln)
+            else:
+                merged.append((o, ln))
+        self.free_list = merged
+
+
+# --------------------------------------------------------------- requests
+
+@dataclass
+class Query:
+    """A catalogue entry: a name, "count" or "exists", and its plans (one
+    for an existence query)."""
+    name: str
+    kind: str
+    plans: list
+
+    def __post_init__(self):
+        if self.kind not in ("count", "exists"):
+            raise ValueError(self.kind)
+        if self.kind == "exists" and len(self.plans) != 1:
+            raise ValueError("an existence query has one plan")
+        if not 1 <= len(self.plans) <= MAX_PLANS:
+            raise ValueError("a query has 1..64 plans")
+
+
+@dataclass
+class Request:
+    rid: int
+    query: Query
+    arrival: float
+    admitted: float | None = None
+    done: float | None = None
+    result: object = None
+    error: str | None = None
+
+
+@dataclass
+class Batch:
+    """Requests admitted together as one launch."""
+    requests: list
+    plans: list                 # unique plans, launch order
+    index: list                 # per request: positions of its plans in `plans`
+    kind: str
+    nbytes: int
+    offset: int = -1
+    slot: int = -1
+    job: object = None
+    t_submit: float = 0.0
+    heavy: bool = False
+
+
+def _merge(requests):
+    plans, pos, index = [], {}, []
+    for r in requests:
+        ix = []
+        for p in r.query.plans:
+            if id(p) not in pos:
+                pos[id(p)] = len(plans)
+                plans.append(p)
+            ix.append(pos[id(p)])
+        index.append(ix)
+    return plans, index
+
+
+@dataclass
+class Policy:
+    """Cost model of admission.  est maps id(plan) to the estimated duration
+    (ms) of a launch of that plan alone at the server's grid; a plan with no
+    estimate costs 0.  A request is heavy when its plans cost more than
+    light_ms.  Launches are formed within one class, so light requests never
+    wait behind a heavy one in the same launch, and requests with new plans
+    join a launch only while its estimated cost stays within
+    max(head's cost, merge_cap_ms).  Requests whose plans are already in the
+    launch always join: they add no work."""
+    light_ms: float = 100.0
+    merge_cap_ms: float = 200.0
+    est: dict = field(default_factory=dict)
+
+    def cost(self, plans) -> float:
+        return sum(self.est.get(id(p), 0.0) for p in plans)
+
+    def heavy(self, req) -> bool:
+        return self.cost(req.query.plans) > self.light_ms
+
+    def observe(self, plans, ms: float):
+        """Fold a finished launch's duration into the estimates."""
+        if len(plans) == 1:
+            k = id(plans[0])
+            old = self.est.get(k)
+            self.est[k] = ms if old is None else 0.5 * (old + ms)
+        else:
+            for p in plans:
+                self.est.setdefault(id(p), ms / len(plans))
+
+
+def next_batch(queue, size_of, pool: Pool, policy: Policy | None = None, allow_heavy: bool = True):
+    """Choose the next launch from the queue.
+
+    The head is the oldest request that may start now (heavy requests are
+    skipped while allow_heavy is False).  Count requests of the head's class
+    behind it join its launch while the unique plans stay within 64 and the
+    policy's cost cap holds (existence requests run alone and keep their
+    place).  The launch is cut from the back until its workspace fits.
+    size_of(plans, kind) -> workspace bytes.  Returns (batch, rejected): a
+    Batch (its workspace already carved from the pool) or None when nothing
+    can start now; and the head if it can never fit (larger than the whole
+    pool), else None."""
+    policy = policy or Policy()
+    head = None
+    for r in queue:
+        if allow_heavy or not policy.heavy(r):
+            head = r
+            break
+    if head is None:
+        return None, None
+    heavy = policy.heavy(head)
+    chosen = [head]
+    if head.query.kind == "exists":
+        # the same existence question asked again shares the answer
+        chosen += [r for r in queue if r is not head and r.query.kind == "exists"
+                   and r.query.plans[0] is head.query.plans[0]]
+    else:
+        ids = {id(p) for p in head.query.plans}
+        cost = policy.cost(_merge(chosen)[0])
+        cap = max(cost, policy.merge_cap_ms)
+        for r in queue:
+            if r is head or r.query.kind != "count" or policy.heavy(r) != heavy:
+                continue
+            new = {id(p): p for p in r.query.plans if id(p) not in ids}
+            if len(ids) + len(new) > MAX_PLANS:
+                continue
+            add = policy.cost(new.values())
+            if new and cost + add > cap:
+                continue
+            chosen.append(r)
+            ids |= set(new)
+            cost += add
+    while True:
+        plans, index = _merge(chosen)
+        nbytes = size_of(plans, head.query.kind)
+        if len(chosen) == 1 and nbytes > pool.size:
+            return None, head
+        off = pool.alloc(nbytes)
+        if off is not None:
+            return Batch(requests=chosen, plans=plans, index=index, kind=head.query.kind, nbytes=nbytes,
+                         offset=off, heavy=heavy), None
+        if len(chosen) == 1:
+            return None, None
+        chosen.pop()
+
+
+# ----------------------------------------------------------------- server
+
+class Server:
+    """Admits requests into concurrent launches on one graph (see the module
+    docstring).  Drive it with offer() and pump()."""
+
+    def __init__(self, graph, pool_bytes: int, slots: int = 4, time_limit_ms: int = 0,
+                 policy: Policy | None = None):
+        import torch
+        from . import pg
+        self.pg = pg
+        self.g = graph
+        self.slots = slots
+        self.grid = max(1, graph.resident_waves[0] // slots)
+        self.time_limit_ms = time_limit_ms
+        self.policy = policy or Policy()
+        # heavy launches may hold all slots but one, which stays for light ones
+        self.max_heavy = max(1, slots - 1)
+        dev = f"cuda:{graph.device}"
+        pool_bytes = -(-pool_bytes // ALIGN) * ALIGN
+        # default-priority streams, one per slot
+        self.streams = [torch.cuda.Stream(device=dev) for _ in range(slots)]
+        raw = torch.empty(pool_bytes + ALIGN, dtype=torch.uint8, device=dev)
+        shift = (-raw.data_ptr()) % ALIGN
+        self._raw = raw
+        self.mem = raw[shift:shift + pool_bytes]
+        self.pool = Pool(pool_bytes)
+        torch.cuda.synchronize(dev)
+        self.free_slots = list(range(slots))
+        self.queue = collections.deque()
+        self.inflight = []
+        self.finished = []
+        self._sizes = {}
+        self.launches = 0
+        self.merged_requests = 0
+
+    def size_of(self, plans, kind):
+        key = (tuple(id(p) for p in plans), kind)
+        b = self._sizes.get(key)
+        if b is None:
+            mode = self.pg.PG_JOB_EXISTS if kind == "exists" else self.pg.PG_JOB_COUNT
+            b = self.pg.job_workspace_size(self.g, plans, mode, grid_waves=self.grid)
+            self._sizes[key] = b
+        return b
+
+    def offer(self, req: Request):
+        self.queue.append(req)
+
+    def idle(self) -> bool:
+        return not self.queue and not self.inflight
+
+    def pump(self) -> int:
+        """Retire finished launches, then admit what fits.  Returns the
+        number of requests retired or admitted (0 = nothing to do now)."""
+        pg = self.pg
+        progress = 0
+        for b in list(self.inflight):
+            if b.job.done():
+                progress += self._retire(b)
+        while self.free_slots and self.queue:
+            n_heavy = sum(1 for x in self.inflight if x.heavy)
+            b, rejected = next_batch(self.queue, self.size_of, self.pool, self.policy,
+                                     allow_heavy=n_heavy < self.max_heavy)
+            if rejected is not None:
+                self.queue.remove(rejected)
+                rejected.error = "workspace larger than the pool"
+                rejected.done = time.perf_counter()
+                self.finished.append(rejected)
+                progress += 1
+                continue
+            if b is None:
+                break
+            for r in b.requests:
+                self.queue.remove(r)
+            b.slot = self.free_slots.pop()
+            ws = self.mem[b.offset:b.offset + b.nbytes]
+            mode = pg.PG_JOB_EXISTS if b.kind == "exists" else pg.PG_JOB_COUNT
+            b.t_submit = time.perf_counter()
+            try:
+                b.job = pg.submit(self.g, b.plans, ws, self.streams[b.slot], mode=mode, grid_waves=self.grid,
+                                  time_limit_ms=self.time_limit_ms)
+            except pg.PGError as e:
+                self._release(b)
+                for r in b.requests:
+                    r.error, r.done = str(e), time.perf_counter()
+                    self.finished.append(r)
+                progress += len(b.requests)
+                continue
+            for r in b.requests:
+                r.admitted = b.t_submit
+            self.inflight.append(b)
+            self.launches += 1
+            self.merged_requests += len(b.requests) - 1
+            progress += len(b.requests)
+        return progress
+
+    def _release(self, b):
+        self.pool.free(b.offset)
+        self.free_slots.append(b.slot)
+
+    def _retire(self, b) -> int:
+        err = None
+        try:
+            res, st = b.job.finish()
+            self.policy.observe(b.plans, st["kernel_ms"])
+        except self.pg.PGError as e:
+            err, res = str(e), None
+        t = time.perf_counter()
+        self.inflight.remove(b)
+        self._release(b)
+        for r, ix in zip(b.requests, b.index):
+            r.done = t
+            if err is not None:
+                r.error = err
+            elif b.kind == "exists":
+                r.result = res
+            else:
+                r.result = [res[i] for i in ix]
+            self.finished.append(r)
+        return len(b.requests)
+
+    def drain(self, poll_s: float = 1e-4):
+        while not self.idle():
+            if not self.pump():
+                time.sleep(poll_s)
+
+
+# -------------------------------------------------------------- workloads
+
+def catalogue(pg, pt):
+    """The query catalogue: (name, kind, pattern specs)."""
+    ent = [("triangle", "count", [pt.clique(3)]), ("wedge", "count", [pt.star(3)])]
+    for i, s in enumerate(pt.all_vertex_induced(4)):
+        ent.append((f"induced4_{i}", "count", [s]))
+    ent += [("clique4", "count", [pt.clique(4)]), ("clique5", "count", [pt.clique(5)])]
+    ent += [(f"clique{k}_exists", "exists", [pt.clique(k)]) for k in (6, 8, 10, 12, 14)]
+    ent += [("induced_diamond", "count", [pt.P8_INDUCED_DIAMOND]),
+            ("two_common_friends", "count", [pt.PA_TWO_COMMON_FRIENDS])]
+    trees5 = [s for s in pt.all_edge_induced(4) if s["k"] == 5]
+    ent += [(f"tree5_{i}", "count", [s]) for i, s in enumerate(trees5)]
+    return [Query(name, kind, [pg.plan_pattern(s) for s in specs]) for name, kind, specs in ent]
+
+
+def poisson_arrivals(lam: float, n: int, n_queries: int, seed: int):
+    """Seeded open-loop arrivals: (times in s from the start, catalogue indices)."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = np.cumsum(rng.exponential(1.0 / lam, n))
+    pick = rng.integers(0, n_queries, n)
+    return t, pick
+
+
+def run_open_loop(server: Server, queries, times, picks, progress=None):
+    """Offer request i at times[i] (seconds after the start) and serve until
+    all are finished.  Latency is measured from the scheduled arrival."""
+    n = len(times)
+    t0 = time.perf_counter()
+    reqs, i = [], 0
+    start = len(server.finished)
+    next_report, last_done, last_print = 200, 0, t0
+    while i < n or not server.idle():
+        now = time.perf_counter() - t0
+        while i < n and times[i] <= now:
+            r = Request(i, queries[picks[i]], t0 + times[i])
+            server.offer(r)
+            reqs.append(r)
+            i += 1
+        moved = server.pump()
+        done = len(server.finished) - start
+        if progress and done > last_done and (done >= next_report or time.perf_counter() - last_print > 20):
+            progress(done, n)
+            next_report = done + 200
+            last_print = time.perf_counter()
+        last_done = done
+        if not moved:
+            wait = 1e-4 if i >= n else min(1e-4, max(0.0, times[i] - (time.perf_counter() - t0)))
+            time.sleep(wait)
+    return reqs, t0
+
+
+def summarize(reqs, t0):
+    ok = [r for r in reqs if r.error is None]
+    lat = sorted(1e3 * (r.done - r.arrival) for r in ok)
+
+    def pct(p):
+        if not lat:
+            return None
+        return lat[min(len(lat) - 1, max(0, math.ceil(p / 100 * len(lat)) - 1))]
+
+    end = max((r.done for r in reqs), default=t0)
+    span = max(1e-9, end - t0)
+    matches = sum(sum(r.result) for r in ok if r.query.kind == "count")
+    return {"requests": len(reqs), "completed": len(ok), "errors": len(reqs) - len(ok),
+            "p50_ms": pct(50), "p99_ms": pct(99), "mean_ms": sum(lat) / len(lat) if lat else None,
+            "completed_qps": len(ok) / span, "matches_per_s": matches / span, "span_s": span}
+
+
+def standalone(graph, queries, pool_bytes: int, limit_ms: int, progress=None):
+    """Each query alone on the whole GPU (one slot), with a time limit.
+    Returns {name: (result or None, latency ms, error)}."""
+    out = {}
+    srv = Server(graph, pool_bytes, slots=1, time_limit_ms=limit_ms)
+    for q in queries:
+        r = Request(0, q, time.perf_counter())
+        srv.offer(r)
+        srv.drain()
+        out[q.name] = (r.result, 1e3 * (r.done - r.arrival), r.error)
+        if progress:
+            progress(q.name, *out[q.name])
+    return out
+
+
+def policy_from(queries, alone, slots: int, **kw) -> Policy:
+    """Estimates from standalone latencies: a launch at 1/slots of the grid
+    is taken to last slots times as long."""
+    pol = Policy(**kw)
+    for q in queries:
+        res, ms, err = alone[q.name]
+        if len(q.plans) == 1 and err is None:
+            pol.est[id(q.plans[0])] = ms * slots
+    return pol
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--workload", default="rmat22_64m")
+    ap.add_argument("--qps", default="50,100,200,500")
+    ap.add_argument("--queries", type=int, default=2000)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--pool-mib", type=int, default=4096)
+    ap.add_argument("--limit-ms", type=int, default=10000, help="standalone latency cut-off")
+    ap.add_argument("--mix-limit-ms", type=int, default=120000, help="time limit of one launch in the mix")
+    ap.add_argument("--light-ms", type=float, default=100.0, help="heavy/light cut (ms at a slot's grid)")
+    ap.add_argument("--seed", type=int, default=5)
+    args = ap.parse_args(argv)
+
+    import torch
+    from . import graphgen as gg
+    from . import patterns as pt
+    from . import pg
+
+    def say(*a):
+        print("[serve]", *a, file=sys.stderr, flush=True)
+
+    assert torch.cuda.is_available(), "serving needs a GPU"
+    t = time.perf_counter()
+    edges = gg.workload(args.workload)
+    say(f"generated {args.workload} in {time.perf_counter() - t:.1f} s")
+    t = time.perf_counter()
+    G = pg.load_graph(*edges, device=0)
+    del edges
+    say(f"ingested n={G.n} m={G.m} d_max={G.d_max} in {time.perf_counter() - t:.1f} s")
+    queries = catalogue(pg, pt)
+    pool = args.pool_mib << 20
+    alone = standalone(G, queries, pool, args.limit_ms,
+                       progress=lambda name, res, ms, err: say(f"alone {name}: {ms:.1f} ms "
+                                                               f"{'error ' + err if err else res}"))
+    keep = [q for q in queries if alone[q.name][2] is None]
+    excluded = [q.name for q in queries if q not in keep]
+    head = {"workload": args.workload, "n": G.n, "m": G.m, "d_max": G.d_max, "slots": args.slots,
+            "pool_bytes": pool, "limit_ms": args.limit_ms,
+            "alone_ms": {k: v[1] for k, v in alone.items()}, "excluded": excluded}
+    print(json.dumps({"catalogue": head}), flush=True)
+    for lam in [float(x) for x in args.qps.split(",")]:
+        srv = Server(G, pool, slots=args.slots, time_limit_ms=args.mix_limit_ms,
+                     policy=policy_from(keep, alone, args.slots, light_ms=args.light_ms))
+        times, picks = poisson_arrivals(lam, args.queries, len(keep), args.seed)
+        say(f"lambda {lam:g}: {args.queries} queries over {times[-1]:.1f} s")
+        reqs, t0 = run_open_loop(srv, keep, times, picks,
+                                 progress=lambda d, n: say(f"  {d}/{n} done"))
+        summ = summarize(reqs, t0)
+        mism = sum(1 for r in reqs if r.error is None and r.result != alone[r.query.name][0])
+        summ.update({"qps_offered": lam, "launches": srv.launches, "merged_requests": srv.merged_requests,
+                     "mismatches_vs_alone": mism})
+        print(json.dumps(summ), flush=True)
+        del srv
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,171 @@
+"""GPU tests of the asynchronous job entry points (pg_job_workspace_size,
+pg_submit, pg_job_poll, pg_job_finish), the launch time limit and the
+serving loop: every query gives the same answer alone and in a mix."""
+import json
+import os
+import sys
+import time
+
+import pytest
+
+from paper_2004_02369_amd import graphgen as gg
+from paper_2004_02369_amd import patterns as pt
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pg():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2004_02369_amd import pg as _pg
+    _pg.lib()
+    return _pg
+
+
+@pytest.fixture(scope="module")
+def g_mid(pg):
+    return pg.load_graph(*gg.workload("chunglu_20k_100k"), device=0)
+
+
+def _workspace(nbytes):
+    import torch
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda:0")
+    shift = (-raw.data_ptr()) % 256
+    return raw[shift:shift + nbytes]
+
+
+def test_jobs_match_synchronous_counts_three_streams(pg, g_mid):
+    import torch
+    say("three concurrent count jobs on chunglu_20k_100k")
+    specs = pt.all_vertex_induced(4)
+    plans = [pg.plan_pattern(s) for s in specs]
+    want = pg.count(g_mid, plans)
+    batches = [plans, plans[:2], [pg.plan_pattern(pt.clique(3)), pg.plan_pattern(pt.star(3))]]
+    wants = [want, want[:2], pg.count(g_mid, batches[2])]
+    grid = max(1, g_mid.resident_waves[0] // 3)
+    streams = [torch.cuda.Stream(device="cuda:0") for _ in batches]
+    jobs = []
+    for b, s in zip(batches, streams):
+        nb = pg.job_workspace_size(g_mid, b, grid_waves=grid)
+        jobs.append(pg.submit(g_mid, b, _workspace(nb), s, grid_waves=grid))
+    t0 = time.perf_counter()
+    while not all(j.done() for j in jobs):
+        assert time.perf_counter() - t0 < 60
+        time.sleep(1e-3)
+    for j, w in zip(jobs, wants):
+        got, st = j.finish()
+        assert got == w
+        assert st["grid_waves"] == grid and st["kernel_ms"] > 0
+    with pytest.raises(pg.PGError):
+        jobs[0].finish()
+
+
+def test_exists_jobs(pg, g_mid):
+    import torch
+    s = torch.cuda.Stream(device="cuda:0")
+    for k in (3, 4, 5, 6, 8, 10, 12, 14):
+        say(f"exists job K{k}")
+        p = pg.plan_pattern(pt.clique(k))
+        nb = pg.job_workspace_size(g_mid, [p], pg.PG_JOB_EXISTS)
+        j = pg.submit(g_mid, [p], _workspace(nb), s, mode=pg.PG_JOB_EXISTS)
+        got, _ = j.finish()
+        assert got == pg.exists(g_mid, p)
+    # K_k with k above the largest clique: a full search that finds nothing
+    G = pg.load_graph(*gg.complete(9), device=0)
+    for k, want in ((9, True), (10, False)):
+        p = pg.plan_pattern(pt.clique(k))
+        nb = pg.job_workspace_size(G, [p], pg.PG_JOB_EXISTS)
+        got, _ = pg.submit(G, [p], _workspace(nb), s, mode=pg.PG_JOB_EXISTS).finish()
+        assert got is want
+
+
+def test_job_argument_errors(pg, g_mid):
+    import torch
+    s = torch.cuda.Stream(device="cuda:0")
+    p = pg.plan_pattern(pt.clique(4))
+    nb = pg.job_workspace_size(g_mid, [p])
+    ws = _workspace(nb + 512)
+    with pytest.raises(pg.PGError) as e:
+        pg.submit(g_mid, [p], ws[:nb - 1], s)
+    assert e.value.status == pg.PG_ENOMEM
+    with pytest.raises(pg.PGError) as e:
+        pg.submit(g_mid, [p], ws[4:4 + nb], s)
+    assert e.value.status == pg.PG_EINVAL
+    with pytest.raises(pg.PGError) as e:
+        pg.job_workspace_size(g_mid, [p, p], pg.PG_JOB_EXISTS)
+    assert e.value.status == pg.PG_EINVAL
+    with pytest.raises(pg.PGError):
+        pg.job_workspace_size(g_mid, [p], mode=7)
+    with pytest.raises(pg.PGError):
+        pg.count_ex(g_mid, [p], time_limit_ms=-1)
+
+
+def test_time_limit_stops_and_a_loose_limit_changes_nothing(pg):
+    import torch
+    with open(os.path.join(HERE, "golden", "expected.json")) as f:
+        w = json.load(f)["workloads"]["chunglu_100k_1m"]
+    from oracle import canonical_of_edges
+    say("time limit on chunglu_100k_1m, 6 induced 4-motifs")
+    G = pg.load_graph(*gg.workload("chunglu_100k_1m"), device=0)
+    specs = pt.all_vertex_induced(4)
+    plans = [pg.plan_pattern(s) for s in specs]
+    want = [w["induced4"][str(canonical_of_edges(4, s["edges"]))]["count"] for s in specs]
+    full, st_full = pg.count_ex(G, plans)
+    assert full == want
+    with pytest.raises(pg.PGError) as e:
+        pg.count_ex(G, plans, time_limit_ms=5)
+    assert e.value.status == pg.PG_ETIMEDOUT
+    got, _ = pg.count_ex(G, plans, time_limit_ms=600000)
+    assert got == want
+    # the same through a job: partial run ends early and reports the limit
+    s = torch.cuda.Stream(device="cuda:0")
+    nb = pg.job_workspace_size(G, plans)
+    j = pg.submit(G, plans, _workspace(nb), s, time_limit_ms=5)
+    with pytest.raises(pg.PGError) as e:
+        j.finish()
+    assert e.value.status == pg.PG_ETIMEDOUT
+    j = pg.submit(G, plans, _workspace(nb), s, time_limit_ms=600000)
+    got, st = j.finish()
+    assert got == want
+
+
+def test_serving_alone_equals_in_mix(pg, g_mid):
+    from paper_2004_02369_amd import serve
+    queries = serve.catalogue(pg, pt)
+    say(f"serving mix: {len(queries)} catalogue entries on chunglu_20k_100k")
+    # answers from the synchronous entry points
+    sync = {}
+    for q in queries:
+        sync[q.name] = pg.exists(g_mid, q.plans[0]) if q.kind == "exists" else pg.count(g_mid, q.plans)
+    def biggest(slots):
+        probe = serve.Server(g_mid, 1 << 20, slots=slots)
+        return max(probe.size_of(q.plans, q.kind) for q in queries)
+
+    alone = serve.standalone(g_mid, queries, biggest(1), limit_ms=60000)
+    for q in queries:
+        res, _, err = alone[q.name]
+        assert err is None, (q.name, err)
+        assert res == sync[q.name], q.name
+    # a pool of about two launches: admission has to wait for memory
+    pool = 2 * biggest(3) + 4096
+    srv = serve.Server(g_mid, pool, slots=3, time_limit_ms=120000,
+                       policy=serve.policy_from(queries, alone, 3, light_ms=20.0))
+    times, picks = serve.poisson_arrivals(3000.0, 300, len(queries), seed=11)
+    reqs, t0 = serve.run_open_loop(srv, queries, times, picks)
+    assert len(reqs) == 300 and srv.idle()
+    for r in reqs:
+        assert r.error is None, (r.query.name, r.error)
+        assert r.result == alone[r.query.name][0], r.query.name
+    assert srv.merged_requests > 0          # continuous batching happened
+    assert any(srv.policy.heavy(r) for r in reqs) and not all(srv.policy.heavy(r) for r in reqs)
+    assert srv.pool.used == 0 and sorted(srv.free_slots) == [0, 1, 2]
+    summ = serve.summarize(reqs, t0)
+    say(f"mix: p50 {summ['p50_ms']:.2f} ms, p99 {summ['p99_ms']:.2f} ms, "
+        f"{summ['completed_qps']:.0f} QPS, {srv.launches} launches")
