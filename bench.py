@@ -6,7 +6,9 @@ resident in HBM.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
 One step = one pg_count call over the batch (plan compile cached, launch,
-device reduction, counts back to the host).  Prints one JSON line.
+device reduction, counts back to the host), with the launch knobs the
+autotuner picks for this graph and plan set before the timed region.
+Prints one JSON line.
 """
 import argparse
 import hashlib
@@ -55,8 +57,8 @@ def measured_traffic(kernel_hash):
 def cpu_baseline(g, specs, budget_s=10.0):
     """The oracle's generic matcher on a bounded sample of start vertices of
     the same graph: matches/s = (valid maps / |Aut|) / time, over the six
-    induced motifs.  Start vertices are taken in a seeded random order, in
-    blocks of 4, until the time budget is spent."""
+    induced motifs.  Start vertices are taken in a seeded random order, one
+    at a time, until the time budget is spent."""
     import numpy as np
     import oracle
     og = oracle.Graph.from_tuple(g)
@@ -66,7 +68,7 @@ def cpu_baseline(g, specs, budget_s=10.0):
     sample = rng.permutation(n).astype(np.int32)
     spent, matches, used = 0.0, 0.0, 0
     while spent < budget_s and used < n:
-        roots = sample[used:used + 4]
+        roots = sample[used:used + 1]
         t0 = time.perf_counter()
         for s in specs:
             matches += oracle.valid_maps_from(og, s, roots, threads) / oracle.aut(s)
@@ -86,6 +88,12 @@ def main():
     ap.add_argument("--no-per-pattern", action="store_true", help="skip the one-launch-per-pattern comparison")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM counters) and exit")
+    ap.add_argument("--knobs", default=None, metavar="JSON",
+                    help="launch knobs to time (skips the autotuner), e.g. '{\"chunk\": 16}'")
+    ap.add_argument("--no-tune", action="store_true", help="time the library defaults")
+    ap.add_argument("--tune-budget", type=float, default=40.0, help="autotuner time budget, s")
+    ap.add_argument("--retune", action="store_true", help="ignore the committed tuning record")
+    ap.add_argument("--tune-out", default="", help="write the tuning result to this cache file")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -116,17 +124,40 @@ def main():
     plans = [pg.plan_pattern(s) for s in specs]
     plan_ms = sum(p.info()["plan_ms"] for p in plans)
 
+    # launch knobs: the autotuner's choice for this graph and plan set
+    # (untimed), unless given or disabled
+    tuning = None
+    if args.knobs:
+        knobs = json.loads(args.knobs)
+    elif args.no_tune:
+        knobs = {}
+    else:
+        # the tuning record committed with the package for this graph and
+        # plan set, if its fingerprint matches; else tune now
+        from paper_2004_02369_amd import tune
+        t_tune = time.perf_counter()
+        res = None if args.retune else tune.lookup(G, plans, tune.RECORDS)
+        if res is None:
+            res = tune.autotune(G, plans, budget_s=args.tune_budget,
+                                cache_path=args.tune_out or None)
+        knobs = res["knobs"]
+        tuning = {"record": bool(res.get("cached")), "default_kernel_ms": res["default_ms"],
+                  "tuned_kernel_ms": res["ms"], "trials": len(res["trials"]),
+                  "tune_s": time.perf_counter() - t_tune}
+    knobs = {k: v for k, v in knobs.items() if v}
+
     # merge-model bytes of one launch (counted in a separate, untimed run)
-    counts_b, st_b = pg.count_ex(G, plans, stream=stream, flags=pg.PG_RUN_COUNT_BYTES)
+    flags = knobs.get("flags", 0)
+    counts_b, st_b = pg.count_ex(G, plans, stream=stream, **dict(knobs, flags=flags | pg.PG_RUN_COUNT_BYTES))
     logical_bytes = st_b["logical_bytes"]
 
     for _ in range(args.warmup):
-        pg.count_ex(G, plans, stream=stream)
+        pg.count_ex(G, plans, stream=stream, **knobs)
     torch.cuda.synchronize()
     kernel_ms = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        counts, st = pg.count_ex(G, plans, stream=stream)
+        counts, st = pg.count_ex(G, plans, stream=stream, **knobs)
         kernel_ms.append(st["kernel_ms"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -136,13 +167,17 @@ def main():
     avg_kernel_ms = statistics.mean(kernel_ms)
 
     # batched vs one launch per pattern (same plans, same graph)
+    # (each pattern alone, with the better of the default knobs and the batch's)
     single_ms = []
     if not args.no_per_pattern:
         for p in plans:
-            pg.count_ex(G, [p], stream=stream)
-            t1 = time.perf_counter()
-            pg.count_ex(G, [p], stream=stream)
-            single_ms.append(1e3 * (time.perf_counter() - t1))
+            best = float("inf")
+            for kn in ({}, knobs):
+                pg.count_ex(G, [p], stream=stream, **kn)
+                t1 = time.perf_counter()
+                pg.count_ex(G, [p], stream=stream, **kn)
+                best = min(best, 1e3 * (time.perf_counter() - t1))
+            single_ms.append(best)
 
     khash = kernel_source_hash()
     traffic = measured_traffic(khash)
@@ -163,6 +198,8 @@ def main():
         "config": {"workload": f"Chung-Lu n={w['n']}, m={G.m} unique edges, gamma={w['gamma']}, "
                                f"w_max={w['w_max']}, seed={w['seed']}; 6 induced 4-motifs in one launch",
                    "n": G.n, "m": G.m, "d_max": G.d_max, "patterns": 6, "parallelism": "1 GPU"},
+        "knobs": knobs,
+        "tuning": tuning,
         "counts": counts,
         "kernel_ms": avg_kernel_ms,
         "plan_ms": plan_ms,

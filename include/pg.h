@@ -47,8 +47,12 @@ typedef struct pg_plan pg_plan;
 /* ------------------------------------------------------------------ graph */
 
 typedef struct {
-    int32_t device;       /* HIP device ordinal; -1 = the current device */
-    int32_t reserved[7];  /* must be zero */
+    int32_t device;         /* HIP device ordinal; -1 = the current device */
+    int32_t hub_min_degree; /* rows of this degree or more also get a dense adjacency bitmap
+                               (membership in one load instead of a binary search);
+                               0 = 16, -1 = no bitmaps */
+    int32_t hub_budget_mib; /* HBM for those bitmaps, highest degrees first; 0 = 1024 */
+    int32_t reserved[5];    /* must be zero */
 } pg_options;
 
 typedef struct {
@@ -61,6 +65,8 @@ typedef struct {
     const int32_t *perm;  /* host, n entries: perm[rank] = original id; owned by the graph */
     int32_t resident_waves[2]; /* wavefronts of the matching kernel resident at once on the device
                                   (patterns without / with anti-vertices): the default grid */
+    int32_t hub_count;      /* rows held as bitmaps too (the hub_count highest ranks) */
+    int32_t hub_min_degree; /* smallest degree among them (0 if none) */
 } pg_graph_info_t;
 
 /* Ingest an undirected graph and make it resident on the GPU (Sec. 5.1,
@@ -171,7 +177,10 @@ typedef struct {
     int32_t time_limit_ms; /* stop every wavefront once this long has passed on the device clock
                               since the launch's first wavefront started, and return
                               PG_ETIMEDOUT; 0 = no limit */
-    int32_t reserved[4];   /* must be zero */
+    int32_t hub_min_degree;/* membership tests use the bitmap of rows of at least this degree
+                              (among those the graph holds bitmaps for) and binary search
+                              below it; 0 = every bitmap the graph holds, -1 = none */
+    int32_t reserved[3];   /* must be zero */
 } pg_run_config;
 
 #define PG_RUN_COUNT_BYTES 1  /* also count the merge-model bytes of every set operation */

@@ -93,6 +93,8 @@ struct pg_graph {
     int32_t *up = nullptr;
     uint32_t *hub_bits = nullptr;  // dense adjacency bitmaps of ranks hub_start..n-1
     int32_t hub_start = 0;
+    int64_t hub_min_deg = 0;
+    std::vector<int64_t> hub_deg;  // host: degrees of ranks hub_start..n-1 (ascending)
     int64_t hub_words = 0;
     int16_t *lab = nullptr;
     int32_t *dperm = nullptr;
@@ -129,7 +131,7 @@ struct pg_graph {
 
 namespace {
 
-constexpr int64_t kHubMinDegree = 128;
+constexpr int64_t kHubMinDegree = 16;
 constexpr long long kArenaInts = 32768;  // per wavefront
 constexpr int64_t kHubBudgetBytes = int64_t(1) << 30;
 
@@ -203,9 +205,17 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         *out = nullptr;
         if (n < 1) { set_error("n must be >= 1"); return PG_EINVAL; }
         if (m < 0 || (m > 0 && (!src || !dst))) { set_error("bad edge arrays"); return PG_EINVAL; }
+        int64_t hub_min = kHubMinDegree, hub_budget = kHubBudgetBytes;
         if (opt) {
-            for (int i = 0; i < 7; i++)
+            for (int i = 0; i < 5; i++)
                 if (opt->reserved[i]) { set_error("pg_options.reserved must be zero"); return PG_EINVAL; }
+            if (opt->hub_min_degree < -1 || opt->hub_budget_mib < 0) {
+                set_error("bad hub bitmap options");
+                return PG_EINVAL;
+            }
+            if (opt->hub_min_degree == -1) hub_min = INT64_MAX;
+            else if (opt->hub_min_degree > 0) hub_min = opt->hub_min_degree;
+            if (opt->hub_budget_mib > 0) hub_budget = (int64_t)opt->hub_budget_mib << 20;
         }
         int dev = opt ? opt->device : -1;
         if (dev < 0) PG_HIP(hipGetDevice(&dev));
@@ -320,15 +330,16 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         if ((st = upload(&g->col, col, &g->device_bytes))) return st;
         if ((st = upload(&g->up, up, &g->device_bytes))) return st;
         // hub rows also as dense bitmaps: the highest-degree vertices (rank
-        // order is degree order) with degree >= kHubMinDegree, within a budget
+        // order is degree order) with degree >= hub_min, within a budget
         {
             const int64_t words = ((int64_t)n + 31) / 32;
             int32_t hs = n;
-            while (hs > 0 && rp[hs] - rp[hs - 1] >= kHubMinDegree &&
-                   (int64_t)(n - hs + 1) * words * 4 <= kHubBudgetBytes)
+            while (hs > 0 && rp[hs] - rp[hs - 1] >= hub_min && (int64_t)(n - hs + 1) * words * 4 <= hub_budget)
                 hs--;
             g->hub_start = hs;
             g->hub_words = words;
+            g->hub_min_deg = hs < n ? rp[hs + 1] - rp[hs] : 0;
+            for (int32_t r = hs; r < n; r++) g->hub_deg.push_back(rp[r + 1] - rp[r]);
             if (hs < n) {
                 std::vector<uint32_t> bits((size_t)(n - hs) * (size_t)words, 0u);
                 for (int32_t r = hs; r < n; r++) {
@@ -367,6 +378,8 @@ pg_status pg_graph_info(const pg_graph *g, pg_graph_info_t *out) {
     out->perm = g->perm.data();
     out->resident_waves[0] = g->n_cu * g->blocks_per_cu[0];
     out->resident_waves[1] = g->n_cu * g->blocks_per_cu[1];
+    out->hub_count = g->n - g->hub_start;
+    out->hub_min_degree = g->hub_start < g->n ? (int32_t)g->hub_min_deg : 0;
     return PG_OK;
 }
 
@@ -464,11 +477,11 @@ pg_status check_args(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, 
     for (int i = 0; i < n_plans; i++)
         if (!plans[i]) { set_error("a plan is NULL"); return PG_EINVAL; }
     if (cfg) {
-        if (cfg->grid_waves < 0 || cfg->chunk < 0 || cfg->time_limit_ms < 0) {
+        if (cfg->grid_waves < 0 || cfg->chunk < 0 || cfg->time_limit_ms < 0 || cfg->hub_min_degree < -1) {
             set_error("negative launch knob");
             return PG_EINVAL;
         }
-        for (int i = 0; i < 4; i++)
+        for (int i = 0; i < 3; i++)
             if (cfg->reserved[i]) { set_error("pg_run_config.reserved must be zero"); return PG_EINVAL; }
     }
     return PG_OK;
@@ -513,9 +526,18 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.col = g->col;
     P.ncol = 2 * g->m;
     P.up = g->up;
-    P.hub_bits = g->hub_bits;
+    // bitmaps are held for ranks hub_start..n-1 (degree order); a launch may
+    // use them from a later rank on, binary search below it
+    int32_t hs = g->hub_start;
+    if (cfg && cfg->hub_min_degree == -1) {
+        hs = g->n;
+    } else if (cfg && cfg->hub_min_degree > 0) {
+        const auto it = std::lower_bound(g->hub_deg.begin(), g->hub_deg.end(), (int64_t)cfg->hub_min_degree);
+        hs = g->hub_start + (int32_t)(it - g->hub_deg.begin());
+    }
+    P.hub_bits = hs < g->n ? g->hub_bits + (size_t)(hs - g->hub_start) * (size_t)g->hub_words : nullptr;
     P.hub_words = g->hub_words;
-    P.hub_start = g->hub_start;
+    P.hub_start = hs;
     P.lab = g->lab;
     P.perm = g->dperm;
     P.tsrc = g->tsrc;

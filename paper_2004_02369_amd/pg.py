@@ -37,13 +37,15 @@ class PGError(RuntimeError):
 
 
 class pg_options(ctypes.Structure):
-    _fields_ = [("device", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("device", ctypes.c_int32), ("hub_min_degree", ctypes.c_int32), ("hub_budget_mib", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class pg_graph_info_t(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("d_max", ctypes.c_int32), ("m", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("labelled", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("perm", ctypes.POINTER(ctypes.c_int32)), ("resident_waves", ctypes.c_int32 * 2)]
+                ("perm", ctypes.POINTER(ctypes.c_int32)), ("resident_waves", ctypes.c_int32 * 2),
+                ("hub_count", ctypes.c_int32), ("hub_min_degree", ctypes.c_int32)]
 
 
 class pg_edge(ctypes.Structure):
@@ -71,7 +73,8 @@ class pg_plan_info_t(ctypes.Structure):
 
 class pg_run_config(ctypes.Structure):
     _fields_ = [("grid_waves", ctypes.c_int32), ("chunk", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("time_limit_ms", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("time_limit_ms", ctypes.c_int32), ("hub_min_degree", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class pg_run_stats(ctypes.Structure):
@@ -158,6 +161,7 @@ class Graph:
         self.device = info.device
         self.perm = np.ctypeslib.as_array(info.perm, shape=(info.n,)).copy()
         self.resident_waves = (int(info.resident_waves[0]), int(info.resident_waves[1]))
+        self.hub_count, self.hub_min_degree = int(info.hub_count), int(info.hub_min_degree)
 
     def csr(self):
         rp = np.zeros(self.n + 1, dtype=np.int64)
@@ -177,13 +181,15 @@ class Graph:
             pass
 
 
-def load_graph(n, src, dst, labels=None, device: int = -1) -> Graph:
+def load_graph(n, src, dst, labels=None, device: int = -1, hub_min_degree: int = 0, hub_budget_mib: int = 0) -> Graph:
+    """Ingest and upload.  hub_min_degree: rows of at least this degree also
+    get a dense bitmap (0 = library default, -1 = none)."""
     src = np.ascontiguousarray(src, dtype=np.int32)
     dst = np.ascontiguousarray(dst, dtype=np.int32)
     if src.shape != dst.shape:
         raise ValueError("src and dst differ in length")
     lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.int16)
-    opt = pg_options(device=device)
+    opt = pg_options(device=device, hub_min_degree=hub_min_degree, hub_budget_mib=hub_budget_mib)
     h = ctypes.c_void_p()
     _check(lib().pg_load_graph(int(n), len(src), src.ctypes.data, dst.ctypes.data,
                                None if lab is None else lab.ctypes.data, ctypes.byref(opt), ctypes.byref(h)))
@@ -279,13 +285,25 @@ def plan_pattern(spec, mode: int = PG_PLAN_AUTO) -> Plan:
 
 # --------------------------------------------------------------- counting
 
-def count_ex(graph: Graph, plans, stream=None, grid_waves=0, chunk=0, flags=0, time_limit_ms=0):
-    """Counts and stats of one launch.  With a time limit, a run that hits it
-    raises PGError with status PG_ETIMEDOUT."""
+RUN_KNOBS = ("grid_waves", "chunk", "flags", "time_limit_ms", "hub_min_degree")
+
+
+def run_config(**kw) -> pg_run_config:
+    """pg_run_config from keyword knobs (RUN_KNOBS); 0 = library default."""
+    bad = set(kw) - set(RUN_KNOBS)
+    if bad:
+        raise TypeError(f"unknown launch knobs {sorted(bad)}")
+    return pg_run_config(**{k: int(v) for k, v in kw.items()})
+
+
+def count_ex(graph: Graph, plans, stream=None, **knobs):
+    """Counts and stats of one launch.  knobs: grid_waves, chunk, flags,
+    time_limit_ms, hub_min_degree (pg_run_config).  A run that reaches its
+    time limit raises PGError with status PG_ETIMEDOUT."""
     plans = list(plans)
     arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
     out = (ctypes.c_uint64 * len(plans))()
-    cfg = pg_run_config(grid_waves=grid_waves, chunk=chunk, flags=flags, time_limit_ms=time_limit_ms)
+    cfg = run_config(**knobs)
     st = pg_run_stats()
     _check(lib().pg_count_ex(graph._h, arr, len(plans), out, ctypes.byref(cfg), ctypes.byref(st),
                              _stream_ptr(stream)))
@@ -338,10 +356,10 @@ def match(graph: Graph, plan: Plan, fn) -> tuple[int, bool]:
 
 # ------------------------------------------------------- asynchronous jobs
 
-def job_workspace_size(graph: Graph, plans, mode=PG_JOB_COUNT, grid_waves=0, chunk=0, flags=0) -> int:
+def job_workspace_size(graph: Graph, plans, mode=PG_JOB_COUNT, **knobs) -> int:
     plans = list(plans)
     arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
-    cfg = pg_run_config(grid_waves=grid_waves, chunk=chunk, flags=flags)  # the time limit does not change it
+    cfg = run_config(**knobs)
     b = ctypes.c_uint64()
     _check(lib().pg_job_workspace_size(graph._h, arr, len(plans), mode, ctypes.byref(cfg), ctypes.byref(b)))
     return int(b.value)
@@ -375,14 +393,13 @@ class Job:
         return (bool(res[0]) if self.mode == PG_JOB_EXISTS else res), _stats(st)
 
 
-def submit(graph: Graph, plans, workspace, stream, mode=PG_JOB_COUNT, grid_waves=0, chunk=0, flags=0,
-           time_limit_ms=0) -> Job:
+def submit(graph: Graph, plans, workspace, stream, mode=PG_JOB_COUNT, **knobs) -> Job:
     """Enqueue one launch on `stream` (a torch.cuda.Stream or raw handle).
     `workspace` is a device uint8 torch tensor of at least
     job_workspace_size() bytes with a 256-byte aligned data pointer."""
     plans = list(plans)
     arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
-    cfg = pg_run_config(grid_waves=grid_waves, chunk=chunk, flags=flags, time_limit_ms=time_limit_ms)
+    cfg = run_config(**knobs)
     h = ctypes.c_void_p()
     _check(lib().pg_submit(graph._h, arr, len(plans), mode, ctypes.byref(cfg),
                            ctypes.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size(),
