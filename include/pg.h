@@ -180,7 +180,11 @@ typedef struct {
     int32_t hub_min_degree;/* membership tests use the bitmap of rows of at least this degree
                               (among those the graph holds bitmaps for) and binary search
                               below it; 0 = every bitmap the graph holds, -1 = none */
-    int32_t reserved[3];   /* must be zero */
+    int32_t batch_max_avg; /* an enumeration level whose children only count is expanded for
+                              up to 64 parents in one flattened pass while those parents
+                              average at most this many candidates, else parent by parent;
+                              0 = always flattened */
+    int32_t reserved[2];   /* must be zero */
 } pg_run_config;
 
 #define PG_RUN_COUNT_BYTES 1  /* also count the merge-model bytes of every set operation */

@@ -477,11 +477,12 @@ pg_status check_args(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, 
     for (int i = 0; i < n_plans; i++)
         if (!plans[i]) { set_error("a plan is NULL"); return PG_EINVAL; }
     if (cfg) {
-        if (cfg->grid_waves < 0 || cfg->chunk < 0 || cfg->time_limit_ms < 0 || cfg->hub_min_degree < -1) {
+        if (cfg->grid_waves < 0 || cfg->chunk < 0 || cfg->time_limit_ms < 0 || cfg->hub_min_degree < -1 ||
+            cfg->batch_max_avg < 0) {
             set_error("negative launch knob");
             return PG_EINVAL;
         }
-        for (int i = 0; i < 3; i++)
+        for (int i = 0; i < 2; i++)
             if (cfg->reserved[i]) { set_error("pg_run_config.reserved must be zero"); return PG_EINVAL; }
     }
     return PG_OK;
@@ -566,6 +567,7 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.n_plans = n_plans;
     P.mode = la.mode;
     P.run_flags = cfg ? cfg->flags : 0;
+    P.batch_max_avg = cfg ? cfg->batch_max_avg : 0;
     return P;
 }
 

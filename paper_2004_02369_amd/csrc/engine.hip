@@ -417,13 +417,11 @@ struct Ctx {
             if (!emit && npos == 1 && N.label < 0 && N.av_count == 0 && ndiff >= 1 && ndiff <= kMaxDiffB &&
                 !(P.run_flags & PG_RUN_NO_MODE_B) && dlen > 0) {
                 // restricted difference rows become the complement's segments
-                long long cost = 0;
                 int k = 0;
                 for (uint32_t s = N.t_diff; s; s &= s - 1, k++) {
                     RowRef r = row(__builtin_ctz(s), l);
                     int32_t n;
                     int32_t b = restrict_row(r, lo, hi, &n);
-                    cost += n;
                     if (k == 0) {
                         sp0 = r.p + b;
                         sl0 = n;
@@ -438,7 +436,32 @@ struct Ctx {
                         so2 = r.owner;
                     }
                 }
-                complement = cost < dlen;
+                // an element of D_k is also probed against D_0..D_k-1: longest
+                // rows first keeps those extra probes on the short rows
+                if (ndiff > 1) {
+                    auto order = [](const int32_t *&pa, int32_t &la, int &oa, const int32_t *&pb, int32_t &lb,
+                                    int &ob) {
+                        if (la < lb) {
+                            const int32_t *tp = pa;
+                            pa = pb;
+                            pb = tp;
+                            const int32_t tl = la;
+                            la = lb;
+                            lb = tl;
+                            const int to = oa;
+                            oa = ob;
+                            ob = to;
+                        }
+                    };
+                    order(sp0, sl0, so0, sp1, sl1, so1);
+                    if (ndiff > 2) {
+                        order(sp1, sl1, so1, sp2, sl2, so2);
+                        order(sp0, sl0, so0, sp1, sl1, so1);
+                    }
+                }
+                // direct: every element of P is probed against each D; by
+                // complement: an element of D_k against P and D_0..D_k-1
+                complement = (long long)sl0 + 2ll * sl1 + 3ll * sl2 < (long long)ndiff * dlen;
             }
             if (P.run_flags & PG_RUN_COUNT_BYTES) {
                 for (uint32_t s = N.t_diff; s; s &= s - 1) {
@@ -777,8 +800,17 @@ struct Ctx {
             }
         }
         // parents whose own driver exceeds the arena go one at a time below;
-        // the rest run in rounds of as many parents as fit the arena
-        const bool big = ok && dlen > P.arena_cap;
+        // the rest run in rounds of as many parents as fit the arena.  With
+        // a batching limit, a batch whose parents average more candidates
+        // than the limit goes one parent at a time as a whole: long lists
+        // already fill the wave, and the flattened pass would only add work.
+        bool big = ok && dlen > P.arena_cap;
+        if (P.batch_max_avg > 0) {
+            int tot = 0;
+            wave_scan_excl(ok && !big ? dlen : 0, lane, &tot);
+            const int nsmall = __popcll(__ballot(ok && !big));
+            if ((long long)tot > (long long)P.batch_max_avg * nsmall) big = ok;
+        }
         const unsigned long long bigmask = __ballot(big);
         unsigned long long remaining = __ballot(ok && !big);
         while (remaining) {

@@ -45,6 +45,7 @@ struct KParams {
     int32_t n_plans;
     int32_t mode;
     int32_t run_flags;
+    int32_t batch_max_avg;     // leaf batching only while parents average at most this many candidates; 0 = always
 };
 
 // with_av: the trie holds anti-vertex checks (selects the kernel variant)

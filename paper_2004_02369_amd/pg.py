@@ -74,7 +74,7 @@ class pg_plan_info_t(ctypes.Structure):
 class pg_run_config(ctypes.Structure):
     _fields_ = [("grid_waves", ctypes.c_int32), ("chunk", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("time_limit_ms", ctypes.c_int32), ("hub_min_degree", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("batch_max_avg", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class pg_run_stats(ctypes.Structure):
@@ -285,7 +285,7 @@ def plan_pattern(spec, mode: int = PG_PLAN_AUTO) -> Plan:
 
 # --------------------------------------------------------------- counting
 
-RUN_KNOBS = ("grid_waves", "chunk", "flags", "time_limit_ms", "hub_min_degree")
+RUN_KNOBS = ("grid_waves", "chunk", "flags", "time_limit_ms", "hub_min_degree", "batch_max_avg")
 
 
 def run_config(**kw) -> pg_run_config:

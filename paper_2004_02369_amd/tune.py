@@ -8,8 +8,10 @@ The knobs (pg_run_config):
 * ``chunk`` -- the largest claim of root tasks; the guided claim grows from 1
   at the costliest tasks to this at the cheapest, so it sets the chunk per
   cost (degree) bucket;
-* ``flags`` -- whether root tasks are expanded in batches of 64 or one at a
-  time (PG_RUN_NO_TASK_BATCH).
+* ``batch_max_avg`` -- a level whose children only count is expanded for up
+  to 64 parents in one flattened pass while the parents average at most this
+  many candidates, parent by parent otherwise (decided per batch);
+* ``flags`` -- PG_RUN_NO_TASK_BATCH turns the flattened pass off everywhere.
 
 The search is coordinate descent over measured kernel times (best of a few
 launches), each trial under a device time limit of a few times the best so
@@ -27,9 +29,10 @@ import time
 SPACE = {
     "hub_min_degree": [0, 32, 64, 128, 256, 1024, -1],
     "chunk": [4, 8, 16, 32, 64, 128],
+    "batch_max_avg": [0, 8, 16, 32, 64, 128, 512],
     "flags": [0, 4],  # 4 = PG_RUN_NO_TASK_BATCH
 }
-DEFAULT = {"hub_min_degree": 0, "chunk": 0, "flags": 0}
+DEFAULT = {"hub_min_degree": 0, "chunk": 0, "batch_max_avg": 0, "flags": 0}
 
 
 class InconsistentCounts(RuntimeError):

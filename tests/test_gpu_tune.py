@@ -49,7 +49,8 @@ def test_knob_settings_match_oracle(pg, case, load_min):
     settings = [{}, {"hub_min_degree": -1}, {"hub_min_degree": 2}, {"hub_min_degree": 37},
                 {"hub_min_degree": 10 ** 6}, {"chunk": 1}, {"chunk": 7}, {"chunk": 500},
                 {"flags": pg.PG_RUN_NO_TASK_BATCH, "chunk": 3, "hub_min_degree": 50},
-                {"grid_waves": 37, "chunk": 2}]
+                {"grid_waves": 37, "chunk": 2}, {"batch_max_avg": 1}, {"batch_max_avg": 40, "chunk": 5},
+                {"batch_max_avg": 3, "hub_min_degree": 20, "chunk": 16}]
     for knobs in settings:
         say(f"load hub_min_degree={load_min} knobs={knobs}")
         assert pg.count(G, plans, **knobs) == want, knobs
