@@ -106,6 +106,7 @@ class Request:
     done: float | None = None
     result: object = None
     error: str | None = None
+    launch: int = -1
 
 
 @dataclass
@@ -121,6 +122,7 @@ class Batch:
     job: object = None
     t_submit: float = 0.0
     heavy: bool = False
+    lid: int = -1
 
 
 def _merge(requests):
@@ -258,6 +260,7 @@ class Server:
         self._sizes = {}
         self.launches = 0
         self.merged_requests = 0
+        self.log = []  # one record per finished launch
 
     def size_of(self, plans, kind):
         key = (tuple(id(p) for p in plans), kind)
@@ -313,6 +316,8 @@ class Server:
                 continue
             for r in b.requests:
                 r.admitted = b.t_submit
+                r.launch = self.launches
+            b.lid = self.launches
             self.inflight.append(b)
             self.launches += 1
             self.merged_requests += len(b.requests) - 1
@@ -324,13 +329,16 @@ class Server:
         self.free_slots.append(b.slot)
 
     def _retire(self, b) -> int:
-        err = None
+        err, st = None, {}
         try:
             res, st = b.job.finish()
             self.policy.observe(b.plans, st["kernel_ms"])
         except self.pg.PGError as e:
             err, res = str(e), None
         t = time.perf_counter()
+        self.log.append({"launch": b.lid, "slot": b.slot, "kind": b.kind, "heavy": b.heavy,
+                         "queries": sorted({r.query.name for r in b.requests}), "requests": len(b.requests),
+                         "t_submit": b.t_submit, "t_done": t, "kernel_ms": st.get("kernel_ms"), "error": err})
         self.inflight.remove(b)
         self._release(b)
         for r, ix in zip(b.requests, b.index):
@@ -415,9 +423,15 @@ def summarize(reqs, t0):
     end = max((r.done for r in reqs), default=t0)
     span = max(1e-9, end - t0)
     matches = sum(sum(r.result) for r in ok if r.query.kind == "count")
+    per_query = {}
+    for name in sorted({r.query.name for r in ok}):
+        ls = sorted(1e3 * (r.done - r.arrival) for r in ok if r.query.name == name)
+        per_query[name] = {"n": len(ls), "p50_ms": ls[(len(ls) - 1) // 2],
+                           "p99_ms": ls[min(len(ls) - 1, max(0, math.ceil(0.99 * len(ls)) - 1))]}
     return {"requests": len(reqs), "completed": len(ok), "errors": len(reqs) - len(ok),
             "p50_ms": pct(50), "p99_ms": pct(99), "mean_ms": sum(lat) / len(lat) if lat else None,
-            "completed_qps": len(ok) / span, "matches_per_s": matches / span, "span_s": span}
+            "completed_qps": len(ok) / span, "matches_per_s": matches / span, "span_s": span,
+            "per_query": per_query}
 
 
 def standalone(graph, queries, pool_bytes: int, limit_ms: int, progress=None):
@@ -457,6 +471,7 @@ def main(argv=None):
     ap.add_argument("--mix-limit-ms", type=int, default=120000, help="time limit of one launch in the mix")
     ap.add_argument("--light-ms", type=float, default=100.0, help="heavy/light cut (ms at a slot's grid)")
     ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--trace", default="", help="write per-launch and per-request records to TRACE.<qps>.json")
     args = ap.parse_args(argv)
 
     import torch
@@ -498,6 +513,11 @@ def main(argv=None):
         summ.update({"qps_offered": lam, "launches": srv.launches, "merged_requests": srv.merged_requests,
                      "mismatches_vs_alone": mism})
         print(json.dumps(summ), flush=True)
+        if args.trace:
+            with open(f"{args.trace}.{lam:g}.json", "w") as f:
+                json.dump({"t0": t0, "launches": srv.log,
+                           "requests": [{"name": r.query.name, "arrival": r.arrival, "admitted": r.admitted,
+                                         "done": r.done, "launch": r.launch, "error": r.error} for r in reqs]}, f)
         del srv
     return 0
 
