@@ -259,12 +259,16 @@ pg_status pg_submit(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, i
                     const pg_run_config *cfg, void *workspace, uint64_t workspace_bytes, void *hip_stream,
                     pg_job **out);
 
-/* Non-blocking: done = 1 once the job's kernel has completed. */
+/* Non-blocking: done = 1 once the job's kernel has completed and its counts
+ * have reached host memory.  At most 64 jobs per graph are in flight
+ * (pg_submit returns PG_ENOMEM beyond that); finish every job before
+ * pg_free_graph. */
 pg_status pg_job_poll(pg_job *job, int32_t *done);
 
 /* Wait for the job, write its counts (host, n_plans entries; for an
  * existence job counts[0] = 1 if a match exists, else 0) and release the
- * job handle (not the workspace). */
+ * job handle (not the workspace).  After pg_job_poll has reported done,
+ * this makes no further GPU call and does not wait. */
 pg_status pg_job_finish(pg_job *job, uint64_t *counts, pg_run_stats *stats);
 
 /* Thread-local message for the last error on this thread ("" if none). */

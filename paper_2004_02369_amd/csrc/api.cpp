@@ -67,14 +67,11 @@ struct pg_job {
     int32_t mode = 0;
     unsigned long long *ctl = nullptr;  // in the caller's workspace
     hipStream_t s = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEvent_t e0 = nullptr, ek = nullptr, e1 = nullptr;  // kernel start, kernel end, counts on the host
     std::chrono::steady_clock::time_point t_submit;
     bool enqueued = false;  // work is on the stream that reads L.image
-    ~pg_job() {
-        if (enqueued) (void)hipStreamSynchronize(s);
-        if (e0) edestroy(e0);
-        if (e1) edestroy(e1);
-    }
+    int ctl_slot = -1;      // this job's block of the graph's pinned control blocks
+    ~pg_job();
 };
 
 struct pg_graph {
@@ -103,6 +100,12 @@ struct pg_graph {
     int64_t device_bytes = 0;
     // per-call buffers, grown on demand
     std::mutex mu;
+    // asynchronous jobs: each copies its control block back into one of
+    // these pinned host blocks on its own stream, so finishing it needs no
+    // further GPU call
+    unsigned long long *ctl_host = nullptr;
+    std::vector<int> ctl_free;
+    std::mutex job_mu;
     int32_t *scratch = nullptr;
     size_t scratch_ints = 0;
     void *trie_buf = nullptr;
@@ -126,8 +129,20 @@ struct pg_graph {
         dfree(scratch);
         dfree(trie_buf);
         dfree(ctl);
+        if (ctl_host) (void)hipHostFree(ctl_host);
     }
 };
+
+inline pg_job::~pg_job() {
+    if (enqueued) (void)hipStreamSynchronize(s);
+    if (e0) edestroy(e0);
+    if (ek) edestroy(ek);
+    if (e1) edestroy(e1);
+    if (ctl_slot >= 0) {
+        std::lock_guard<std::mutex> lock(g->job_mu);
+        g->ctl_free.push_back(ctl_slot);
+    }
+}
 
 namespace {
 
@@ -142,6 +157,7 @@ constexpr int kCtlBytes = 66;
 constexpr int kCtlFlags = 67;  // four int32 in two slots: overflow, stop, timed out, unused
 constexpr int kCtlStart = 69;  // device wall clock at the first wavefront's start
 constexpr int kCtlWords = 70;
+constexpr int kJobSlots = 64;  // asynchronous jobs in flight per graph
 
 struct DeviceGuard {
     int prev = -1;
@@ -825,6 +841,22 @@ pg_status pg_submit(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, i
         }
         DeviceGuard guard(g->device);
         j->g = g;
+        {
+            std::lock_guard<std::mutex> lock(g->job_mu);
+            if (!g->ctl_host) {
+                void *h = nullptr;
+                PG_HIP(hipHostMalloc(&h, (size_t)kJobSlots * kCtlWords * sizeof(unsigned long long),
+                                     hipHostMallocDefault));
+                g->ctl_host = static_cast<unsigned long long *>(h);
+                for (int i = kJobSlots - 1; i >= 0; i--) g->ctl_free.push_back(i);
+            }
+            if (g->ctl_free.empty()) {
+                set_error("too many jobs in flight on this graph (64)");
+                return PG_ENOMEM;
+            }
+            j->ctl_slot = g->ctl_free.back();
+            g->ctl_free.pop_back();
+        }
         j->n_plans = n_plans;
         j->mode = mode;
         j->s = reinterpret_cast<hipStream_t>(hip_stream);
@@ -840,6 +872,7 @@ pg_status pg_submit(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, i
         la.mode = mode == PG_JOB_EXISTS ? pg::kModeExists : pg::kModeCount;
         const pg::KParams P = params(g, j->L, trie, j->ctl, scratch, la, n_plans, cfg);
         PG_HIP(hipEventCreate(&j->e0));
+        PG_HIP(hipEventCreate(&j->ek));
         PG_HIP(hipEventCreate(&j->e1));
         PG_HIP(hipEventRecord(j->e0, j->s));
         hipError_t le = pg::launch_match(P, j->L.grid, j->L.with_av, j->s);
@@ -847,6 +880,9 @@ pg_status pg_submit(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, i
             set_error(std::string("kernel launch: ") + hipGetErrorString(le));
             return PG_EDEVICE;
         }
+        PG_HIP(hipEventRecord(j->ek, j->s));
+        PG_HIP(hipMemcpyAsync(g->ctl_host + (size_t)j->ctl_slot * kCtlWords, j->ctl,
+                              kCtlWords * sizeof(unsigned long long), hipMemcpyDeviceToHost, j->s));
         PG_HIP(hipEventRecord(j->e1, j->s));
         *out = j.release();
         return PG_OK;
@@ -873,12 +909,11 @@ pg_status pg_job_finish(pg_job *j, uint64_t *counts, pg_run_stats *stats) {
     if (!j) { set_error("NULL job"); return PG_EINVAL; }
     std::unique_ptr<pg_job> own(j);
     DeviceGuard guard(j->g->device);
-    unsigned long long ctl[kCtlWords];
-    PG_HIP(hipMemcpyAsync(ctl, j->ctl, sizeof(ctl), hipMemcpyDeviceToHost, j->s));
-    PG_HIP(hipStreamSynchronize(j->s));
+    PG_HIP(hipEventSynchronize(j->e1));
     j->enqueued = false;
+    const unsigned long long *ctl = j->g->ctl_host + (size_t)j->ctl_slot * kCtlWords;
     float ms = 0.f;
-    PG_HIP(hipEventElapsedTime(&ms, j->e0, j->e1));
+    PG_HIP(hipEventElapsedTime(&ms, j->e0, j->ek));
     if (stats) {
         stats->kernel_ms = ms;
         stats->total_ms =

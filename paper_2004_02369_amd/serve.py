@@ -227,16 +227,45 @@ def next_batch(queue, size_of, pool: Pool, policy: Policy | None = None, allow_h
 
 # ----------------------------------------------------------------- server
 
+_STREAMS = {}
+
+
+def hw_queues() -> int:
+    """Hardware queues HIP gives this process per device (its default is 4)."""
+    import os
+    try:
+        return max(1, int(os.environ.get("GPU_MAX_HW_QUEUES", "4")))
+    except ValueError:
+        return 4
+
+
+def default_slots() -> int:
+    # one queue stays with the default stream; more streams than queues
+    # would share queues, and work on a shared queue runs in order
+    return max(1, min(4, hw_queues() - 1))
+
+
+def slot_streams(device: str, n: int):
+    """The first n of this process's serving streams on `device`, created
+    once and reused (default priority)."""
+    import torch
+    pool = _STREAMS.setdefault(device, [])
+    while len(pool) < n:
+        pool.append(torch.cuda.Stream(device=device))
+    return pool[:n]
+
+
 class Server:
     """Admits requests into concurrent launches on one graph (see the module
     docstring).  Drive it with offer() and pump()."""
 
-    def __init__(self, graph, pool_bytes: int, slots: int = 4, time_limit_ms: int = 0,
+    def __init__(self, graph, pool_bytes: int, slots: int | None = None, time_limit_ms: int = 0,
                  policy: Policy | None = None):
         import torch
         from . import pg
         self.pg = pg
         self.g = graph
+        slots = slots or default_slots()
         self.slots = slots
         self.grid = max(1, graph.resident_waves[0] // slots)
         self.time_limit_ms = time_limit_ms
@@ -245,8 +274,7 @@ class Server:
         self.max_heavy = max(1, slots - 1)
         dev = f"cuda:{graph.device}"
         pool_bytes = -(-pool_bytes // ALIGN) * ALIGN
-        # default-priority streams, one per slot
-        self.streams = [torch.cuda.Stream(device=dev) for _ in range(slots)]
+        self.streams = slot_streams(dev, slots)
         raw = torch.empty(pool_bytes + ALIGN, dtype=torch.uint8, device=dev)
         shift = (-raw.data_ptr()) % ALIGN
         self._raw = raw
@@ -465,7 +493,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="rmat22_64m")
     ap.add_argument("--qps", default="50,100,200,500")
     ap.add_argument("--queries", type=int, default=2000)
-    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--slots", type=int, default=0, help="concurrent launches (0 = hardware queues - 1)")
     ap.add_argument("--pool-mib", type=int, default=4096)
     ap.add_argument("--limit-ms", type=int, default=10000, help="standalone latency cut-off")
     ap.add_argument("--mix-limit-ms", type=int, default=120000, help="time limit of one launch in the mix")
@@ -497,13 +525,14 @@ def main(argv=None):
                                                                f"{'error ' + err if err else res}"))
     keep = [q for q in queries if alone[q.name][2] is None]
     excluded = [q.name for q in queries if q not in keep]
-    head = {"workload": args.workload, "n": G.n, "m": G.m, "d_max": G.d_max, "slots": args.slots,
+    slots = args.slots or default_slots()
+    head = {"workload": args.workload, "n": G.n, "m": G.m, "d_max": G.d_max, "slots": slots,
             "pool_bytes": pool, "limit_ms": args.limit_ms,
             "alone_ms": {k: v[1] for k, v in alone.items()}, "excluded": excluded}
     print(json.dumps({"catalogue": head}), flush=True)
     for lam in [float(x) for x in args.qps.split(",")]:
-        srv = Server(G, pool, slots=args.slots, time_limit_ms=args.mix_limit_ms,
-                     policy=policy_from(keep, alone, args.slots, light_ms=args.light_ms))
+        srv = Server(G, pool, slots=slots, time_limit_ms=args.mix_limit_ms,
+                     policy=policy_from(keep, alone, slots, light_ms=args.light_ms))
         times, picks = poisson_arrivals(lam, args.queries, len(keep), args.seed)
         say(f"lambda {lam:g}: {args.queries} queries over {times[-1]:.1f} s")
         reqs, t0 = run_open_loop(srv, keep, times, picks,

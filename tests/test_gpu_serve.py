@@ -10,6 +10,7 @@ import pytest
 
 from paper_2004_02369_amd import graphgen as gg
 from paper_2004_02369_amd import patterns as pt
+from paper_2004_02369_amd import serve
 
 pytestmark = pytest.mark.gpu
 
@@ -50,7 +51,7 @@ def test_jobs_match_synchronous_counts_three_streams(pg, g_mid):
     batches = [plans, plans[:2], [pg.plan_pattern(pt.clique(3)), pg.plan_pattern(pt.star(3))]]
     wants = [want, want[:2], pg.count(g_mid, batches[2])]
     grid = max(1, g_mid.resident_waves[0] // 3)
-    streams = [torch.cuda.Stream(device="cuda:0") for _ in batches]
+    streams = serve.slot_streams("cuda:0", len(batches))
     jobs = []
     for b, s in zip(batches, streams):
         nb = pg.job_workspace_size(g_mid, b, grid_waves=grid)
@@ -69,7 +70,7 @@ def test_jobs_match_synchronous_counts_three_streams(pg, g_mid):
 
 def test_exists_jobs(pg, g_mid):
     import torch
-    s = torch.cuda.Stream(device="cuda:0")
+    s = serve.slot_streams("cuda:0", 1)[0]
     for k in (3, 4, 5, 6, 8, 10, 12, 14):
         say(f"exists job K{k}")
         p = pg.plan_pattern(pt.clique(k))
@@ -88,7 +89,7 @@ def test_exists_jobs(pg, g_mid):
 
 def test_job_argument_errors(pg, g_mid):
     import torch
-    s = torch.cuda.Stream(device="cuda:0")
+    s = serve.slot_streams("cuda:0", 1)[0]
     p = pg.plan_pattern(pt.clique(4))
     nb = pg.job_workspace_size(g_mid, [p])
     ws = _workspace(nb + 512)
@@ -125,7 +126,7 @@ def test_time_limit_stops_and_a_loose_limit_changes_nothing(pg):
     got, _ = pg.count_ex(G, plans, time_limit_ms=600000)
     assert got == want
     # the same through a job: partial run ends early and reports the limit
-    s = torch.cuda.Stream(device="cuda:0")
+    s = serve.slot_streams("cuda:0", 1)[0]
     nb = pg.job_workspace_size(G, plans)
     j = pg.submit(G, plans, _workspace(nb), s, time_limit_ms=5)
     with pytest.raises(pg.PGError) as e:
@@ -136,8 +137,38 @@ def test_time_limit_stops_and_a_loose_limit_changes_nothing(pg):
     assert got == want
 
 
+def test_short_job_finishes_beside_a_long_one(pg):
+    """A short launch on another slot stream completes, and is seen as done,
+    while a long one still runs: the slots really overlap."""
+    say("short job beside a long one on chunglu_100k_1m")
+    G = pg.load_graph(*gg.workload("chunglu_100k_1m"), device=0)
+    grid = max(1, G.resident_waves[0] // serve.default_slots())
+    long_plans = [pg.plan_pattern(s) for s in pt.all_vertex_induced(4)]
+    short_plans = [pg.plan_pattern(pt.clique(3))]
+    s_long, s_short = serve.slot_streams("cuda:0", 2)
+    w_long = _workspace(pg.job_workspace_size(G, long_plans, grid_waves=grid))
+    w_short = _workspace(pg.job_workspace_size(G, short_plans, grid_waves=grid))
+    want_short = pg.count(G, short_plans)
+    import torch
+    torch.cuda.synchronize()
+    j_long = pg.submit(G, long_plans, w_long, s_long, grid_waves=grid)
+    t0 = time.perf_counter()
+    j_short = pg.submit(G, short_plans, w_short, s_short, grid_waves=grid)
+    while not j_short.done():
+        assert time.perf_counter() - t0 < 60
+        time.sleep(1e-4)
+    t_short = time.perf_counter() - t0
+    got, _ = j_short.finish()
+    t_fin = time.perf_counter() - t0
+    long_running = not j_long.done()
+    j_long.finish()
+    say(f"short job seen done after {1e3 * t_short:.1f} ms, finished at {1e3 * t_fin:.1f} ms; long still running: "
+        f"{long_running}")
+    assert got == want_short
+    assert long_running
+
+
 def test_serving_alone_equals_in_mix(pg, g_mid):
-    from paper_2004_02369_amd import serve
     queries = serve.catalogue(pg, pt)
     say(f"serving mix: {len(queries)} catalogue entries on chunglu_20k_100k")
     # answers from the synchronous entry points
