@@ -81,6 +81,8 @@ def _L():
         lib.orc_noninduced4.restype = ctypes.c_int
         lib.orc_noninduced4.argtypes = [vp, ctypes.c_int, vp, vp]
         lib.orc_triangles_per_vertex.argtypes = [vp, vp]
+        lib.orc_domains.restype = ctypes.c_int
+        lib.orc_domains.argtypes = [vp, ctypes.POINTER(_Pattern), ctypes.c_int, vp, vp]
         _lib = lib
     return _lib
 
@@ -224,6 +226,26 @@ def count(g: Graph, spec, threads: int | None = None) -> int:
     if rc == -3:
         raise AssertionError("valid-map count not divisible by |Aut|")
     return (hi.value << 64) | lo.value
+
+
+def domains(g: Graph, spec, threads: int | None = None, members: bool = False):
+    """MNI domains (Sec. 2): sizes[u] = |{m(u) : m a valid map}| for each
+    regular vertex u; with members=True also a (k, n) 0/1 array."""
+    k = int(spec["k"])
+    sizes = np.zeros(k, dtype=np.int64)
+    mem = np.zeros((k, g.n), dtype=np.uint8) if members else None
+    rc = _L().orc_domains(g._h, ctypes.byref(_to_struct(spec)), threads or default_threads(), sizes.ctypes.data,
+                          mem.ctypes.data if members else None)
+    if rc == -1:
+        raise ValueError("pattern is not connected by true edges")
+    if rc:
+        raise MemoryError("orc_domains")
+    return (sizes.tolist(), mem) if members else sizes.tolist()
+
+
+def mni_support(g: Graph, spec, threads: int | None = None) -> int:
+    """Minimum node image support: the smallest domain."""
+    return min(domains(g, spec, threads))
 
 
 # ------------------------------------------------------------ motif classes

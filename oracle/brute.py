@@ -125,3 +125,9 @@ def induced_subsets_count(graph, k, pattern_edges) -> int:
 
 def typed_aut(spec) -> int:
     return _typed_aut(spec)
+
+
+def domains_brute(graph, spec, labels=None) -> list[int]:
+    """|{m(u) : m valid}| for every regular vertex u, over every injective map."""
+    maps = canonical_maps(graph, spec, labels)
+    return [len({m[u] for m in maps}) for u in range(spec["k"])]

@@ -345,6 +345,103 @@ int orc_valid_maps(const orc_graph *g, const orc_pattern *p, int nthreads, uint6
     return orc_valid_maps_roots(g, p, nthreads, NULL, 0, lo, hi);
 }
 
+/* ---------------------------------------------------------- MNI domains */
+
+/* Sec. 2 (support of a pattern): dom(u) is the set of data vertices that u
+ * is mapped to by at least one valid map.  Written from that definition:
+ * for every pattern vertex u and every data vertex v, search for one valid
+ * map with u -> v (the same checks as match_rec, stopping at the first).
+ * This is test infrastructure: it shares nothing with the GPU path. */
+typedef struct {
+    match_job J;          /* order[0] = u, BFS order over true edges from u */
+    uint8_t *member;      /* n entries: 1 if v in dom(u) */
+} dom_job;
+
+static int exists_rec(match_job *J, int32_t *img, int pos) {
+    const orc_graph *g = J->g;
+    const orc_pattern *p = J->p;
+    if (pos == p->k) {
+        for (int a = 0; a < p->n_av; a++)
+            if (!av_ok(g, p, a, img)) return 0;
+        return 1;
+    }
+    int u = J->order[pos];
+    int32_t par = img[J->order[J->parent[pos]]];
+    for (int64_t e = g->off[par]; e < g->off[par + 1]; e++) {
+        int32_t x = g->adj[e];
+        int ok = 1;
+        if (p->label[u] != -1 && (!g->label || g->label[x] != p->label[u])) ok = 0;
+        for (int q = 0; q < pos && ok; q++) {
+            int w = J->order[q];
+            if (img[w] == x) ok = 0;
+            else if ((p->edge[u] >> w & 1u) && !has_edge(g, x, img[w])) ok = 0;
+            else if ((p->anti[u] >> w & 1u) && has_edge(g, x, img[w])) ok = 0;
+        }
+        if (!ok) continue;
+        img[u] = x;
+        if (exists_rec(J, img, pos + 1)) return 1;
+    }
+    return 0;
+}
+
+static void *dom_worker(void *arg) {
+    dom_job *D = arg;
+    match_job *J = &D->J;
+    const orc_pattern *p = J->p;
+    int32_t img[16];
+    for (;;) {
+        int64_t v = atomic_fetch_add(&J->cursor, 1);
+        if (v >= J->g->n) break;
+        int u0 = J->order[0];
+        if (p->label[u0] != -1 && (!J->g->label || J->g->label[v] != p->label[u0])) continue;
+        img[u0] = (int32_t)v;
+        D->member[v] = (uint8_t)exists_rec(J, img, 1);
+    }
+    return NULL;
+}
+
+/* sizes[u] = |dom(u)| for u = 0..k-1; member: NULL or k*n bytes (row u:
+ * membership of each data vertex in dom(u)).  Returns -1 if the regular
+ * vertices are not connected by true edges. */
+int orc_domains(const orc_graph *g, const orc_pattern *p, int nthreads, int64_t *sizes, uint8_t *member) {
+    uint8_t *buf = (uint8_t *)calloc((size_t)(g->n > 0 ? g->n : 1), 1);
+    if (!buf) return -2;
+    for (int u = 0; u < p->k; u++) {
+        dom_job D;
+        memset(&D, 0, sizeof(D));
+        D.J.g = g;
+        D.J.p = p;
+        D.member = buf;
+        memset(buf, 0, (size_t)g->n);
+        int seen[16] = {0};
+        int head = 0, tail = 0;
+        D.J.order[tail++] = u;
+        seen[u] = 1;
+        D.J.parent[0] = -1;
+        while (head < tail) {
+            int x = D.J.order[head++];
+            for (int y = 0; y < p->k; y++)
+                if ((p->edge[x] >> y & 1u) && !seen[y]) {
+                    seen[y] = 1;
+                    D.J.parent[tail] = head - 1;
+                    D.J.order[tail++] = y;
+                }
+        }
+        if (tail != p->k) { free(buf); return -1; }
+        atomic_init(&D.J.cursor, 0);
+        int nt = nthreads < 1 ? 1 : (nthreads > 256 ? 256 : nthreads);
+        pthread_t th[256];
+        for (int t = 0; t < nt; t++) pthread_create(&th[t], NULL, dom_worker, &D);
+        for (int t = 0; t < nt; t++) pthread_join(th[t], NULL);
+        int64_t c = 0;
+        for (int32_t v = 0; v < g->n; v++) c += buf[v];
+        sizes[u] = c;
+        if (member) memcpy(member + (size_t)u * (size_t)g->n, buf, (size_t)g->n);
+    }
+    free(buf);
+    return 0;
+}
+
 /* count(G, p) = |valid maps| / |Aut_t(p)|.  Returns 0 on success, -1 for a
  * disconnected pattern, -2 if |Aut_t| is out of the exhaustive range, -3 if
  * the division is not exact (which would mean a bug in this file). */
