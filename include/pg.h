@@ -125,7 +125,13 @@ typedef struct {
 
 typedef struct {
     int32_t mode;          /* PG_PLAN_* */
-    int32_t reserved[7];   /* must be zero */
+    int32_t anchored;      /* 1: plan for the domain of regular vertex `anchor` (MNI support,
+                              Sec. 2 and 5.5): the anchor is kept in the core and symmetry
+                              is broken only by automorphisms that fix it, so every data
+                              vertex the anchor can map to is reached; counts are then
+                              valid maps / |stabiliser of the anchor| */
+    int32_t anchor;        /* the anchored regular vertex, 0..k-1 */
+    int32_t reserved[5];   /* must be zero */
 } pg_plan_options;
 
 typedef struct {
@@ -144,6 +150,7 @@ typedef struct {
     int32_t orbit_vertex[16];
     int32_t mode_used;        /* PG_PLAN_LINEAR_EXT or PG_PLAN_PARTIAL_ORDER */
     double plan_ms;           /* host time to build the plan */
+    int32_t anchor;           /* anchored vertex, -1 if none (then aut is its stabiliser's order) */
 } pg_plan_info_t;
 
 /* Build the exploration plan of a pattern (Sec. 4.1 Fig. "Computing
@@ -231,6 +238,18 @@ pg_status pg_enumerate(pg_graph *g, const pg_plan *plan, int32_t *out, uint64_t 
  * stream; the callback runs on the calling host thread. */
 typedef int (*pg_match_cb)(const int32_t *ids, int32_t k, void *user);
 pg_status pg_match(pg_graph *g, const pg_plan *plan, pg_match_cb cb, void *user, uint64_t *n_matches);
+
+/* MNI domains (Sec. 2, frequent subgraph mining; Sec. 5.5): for each plan p,
+ * compiled anchored at regular vertex u_p (pg_plan_options.anchored), the
+ * number of distinct data vertices v such that some valid map sends u_p to
+ * v, i.e. |dom(u_p)| over all embeddings.  The MNI support of a pattern is
+ * the minimum of |dom(u)| over its vertices; one anchor per automorphism
+ * orbit suffices.  sizes: host, n_plans entries.  counts: host, n_plans
+ * entries or NULL (valid maps / |stabiliser of the anchor|).  One launch
+ * over all plans (at most 64); the graph holds n_plans n-bit bitmaps for it.
+ * PG_EINVAL if a plan is not anchored.  Synchronous on hip_stream. */
+pg_status pg_domain_sizes(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *sizes,
+                          uint64_t *counts, const pg_run_config *cfg, void *hip_stream);
 
 /* ------------------------------------------------------ asynchronous jobs
  *

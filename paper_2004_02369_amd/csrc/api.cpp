@@ -100,6 +100,9 @@ struct pg_graph {
     int64_t device_bytes = 0;
     // per-call buffers, grown on demand
     std::mutex mu;
+    uint32_t *marks = nullptr;              // domain bitmaps (pg_domain_sizes)
+    unsigned long long *mark_cnt = nullptr;
+    size_t mark_cap = 0;                    // words held by marks
     // asynchronous jobs: each copies its control block back into one of
     // these pinned host blocks on its own stream, so finishing it needs no
     // further GPU call
@@ -129,6 +132,8 @@ struct pg_graph {
         dfree(scratch);
         dfree(trie_buf);
         dfree(ctl);
+        dfree(marks);
+        dfree(mark_cnt);
         if (ctl_host) (void)hipHostFree(ctl_host);
     }
 };
@@ -418,7 +423,7 @@ pg_status pg_plan_pattern_ex(const pg_pattern_desc *p, const pg_plan_options *op
         if (!out) { set_error("out is NULL"); return PG_EINVAL; }
         *out = nullptr;
         if (opt)
-            for (int i = 0; i < 7; i++)
+            for (int i = 0; i < 5; i++)
                 if (opt->reserved[i]) { set_error("pg_plan_options.reserved must be zero"); return PG_EINVAL; }
         static std::atomic<uint64_t> next_uid{1};
         std::unique_ptr<pg_plan> plan(new pg_plan());
@@ -484,6 +489,9 @@ struct LaunchArgs {
     int mode = pg::kModeCount;
     int32_t *out = nullptr;
     uint64_t cap = 0;
+    uint64_t *sizes = nullptr;     // domains: host, n_plans domain sizes (marks on)
+    uint32_t *mark_dev = nullptr;  // set by run(): the graph's mark bitmaps
+    long long mark_words = 0;
 };
 
 pg_status check_args(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, const pg_run_config *cfg) {
@@ -584,6 +592,8 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.mode = la.mode;
     P.run_flags = cfg ? cfg->flags : 0;
     P.batch_max_avg = cfg ? cfg->batch_max_avg : 0;
+    P.mark = la.mark_dev;
+    P.mark_words = la.mark_words;
     return P;
 }
 
@@ -651,7 +661,30 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
         g->scratch_ints = L.scratch_ints;
     }
     PG_HIP(hipMemsetAsync(g->ctl, 0, kCtlWords * sizeof(unsigned long long), s));
-    const pg::KParams P = params(g, L, g->trie_buf, g->ctl, g->scratch, la, n_plans, cfg);
+    LaunchArgs la2 = la;
+    const long long words = ((long long)g->n + 31) / 32;
+    if (la.sizes) {
+        // one n-bit bitmap per plan, plus its popcount
+        const size_t need = (size_t)n_plans * (size_t)words;
+        if (need > g->mark_cap) {
+            dfree(g->marks);
+            dfree(g->mark_cnt);
+            g->marks = nullptr;
+            g->mark_cnt = nullptr;
+            g->mark_cap = 0;
+            if (hipMalloc(reinterpret_cast<void **>(&g->marks), need * sizeof(uint32_t)) != hipSuccess ||
+                hipMalloc(reinterpret_cast<void **>(&g->mark_cnt),
+                          pg::kMaxPlansPerLaunch * sizeof(unsigned long long)) != hipSuccess) {
+                set_error("hipMalloc domain bitmaps");
+                return PG_ENOMEM;
+            }
+            g->mark_cap = need;
+        }
+        PG_HIP(hipMemsetAsync(g->marks, 0, need * sizeof(uint32_t), s));
+        la2.mark_dev = g->marks;
+        la2.mark_words = words;
+    }
+    const pg::KParams P = params(g, L, g->trie_buf, g->ctl, g->scratch, la2, n_plans, cfg);
 
     hipEvent_t e0, e1;
     PG_HIP(hipEventCreate(&e0));
@@ -665,9 +698,24 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
         return PG_EDEVICE;
     }
     PG_HIP(hipEventRecord(e1, s));
+    std::vector<unsigned long long> dsz;
+    if (la.sizes) {
+        PG_HIP(hipMemsetAsync(g->mark_cnt, 0, (size_t)n_plans * sizeof(unsigned long long), s));
+        hipError_t pe = pg::launch_popcount(g->marks, words, n_plans, g->mark_cnt, s);
+        if (pe != hipSuccess) {
+            edestroy(e0);
+            edestroy(e1);
+            set_error(std::string("popcount launch: ") + hipGetErrorString(pe));
+            return PG_EDEVICE;
+        }
+        dsz.resize(n_plans);
+        PG_HIP(hipMemcpyAsync(dsz.data(), g->mark_cnt, (size_t)n_plans * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, s));
+    }
     unsigned long long ctl[kCtlWords];
     PG_HIP(hipMemcpyAsync(ctl, g->ctl, sizeof(ctl), hipMemcpyDeviceToHost, s));
     PG_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < dsz.size(); i++) la.sizes[i] = dsz[i];
     float ms = 0.f;
     PG_HIP(hipEventElapsedTime(&ms, e0, e1));
     edestroy(e0);
@@ -730,6 +778,30 @@ pg_status pg_exists(pg_graph *g, const pg_plan *plan, int32_t *found, void *hip_
         return PG_ENOMEM;
     }
     *found = c > 0 ? 1 : 0;
+    return PG_OK;
+}
+
+pg_status pg_domain_sizes(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *sizes,
+                          uint64_t *counts, const pg_run_config *cfg, void *hip_stream) {
+    if (!sizes) { set_error("sizes is NULL"); return PG_EINVAL; }
+    if (plans && n_plans > 0)
+        for (int i = 0; i < n_plans && i < pg::kMaxPlansPerLaunch; i++)
+            if (plans[i] && plans[i]->impl.anchor < 0) {
+                set_error("every plan must be anchored (pg_plan_options.anchored)");
+                return PG_EINVAL;
+            }
+    LaunchArgs la;
+    la.sizes = sizes;
+    std::vector<uint64_t> c((size_t)std::max(0, n_plans));
+    try {
+        pg_status st = run(g, plans, n_plans, c.data(), cfg, nullptr, hip_stream, la, nullptr);
+        if (st) return st;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    }
+    if (counts)
+        for (int i = 0; i < n_plans; i++) counts[i] = c[i];
     return PG_OK;
 }
 

@@ -640,6 +640,12 @@ struct Ctx {
                                                  ? (unsigned long long)L.pcnt[lane]
                                                  : (unsigned long long)(L.pconst[lane] - (int32_t)L.pcnt[lane]);
                 contrib = choose(c, N.group, &ovf);
+                // domains: this prefix has a match, so its anchor's image is in
+                // the anchor's domain
+                if (P.mark && contrib && N.anchor_level >= 0) {
+                    const int32_t v = val(N.anchor_level, lane);
+                    atomicOr(P.mark + (long long)N.plan * P.mark_words + (v >> 5), 1u << (v & 31));
+                }
                 unsigned long long q;
                 if (__builtin_mul_overflow(contrib, N.mult, &q)) ovf = true;
                 contrib = q;
@@ -1277,6 +1283,26 @@ int match_blocks_per_cu(bool with_av) {
                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, match_kernel, 64, 0);
     if (e != hipSuccess || nb < 1) nb = 8;
     return nb;
+}
+
+// rows of bits: out[r] += popcount(bits[r * words .. (r + 1) * words)); one
+// row per blockIdx.y, a grid-stride loop over its words
+__global__ void __launch_bounds__(256) popcount_rows(const uint32_t *bits, long long words,
+                                                     unsigned long long *out) {
+    const uint32_t *row = bits + (long long)blockIdx.y * words;
+    unsigned long long c = 0;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (long long)gridDim.x * blockDim.x)
+        c += (unsigned long long)__popc(row[i]);
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(out + blockIdx.y, c);
+}
+
+hipError_t launch_popcount(const uint32_t *bits, long long words, int rows, unsigned long long *out,
+                           hipStream_t s) {
+    const long long blocks = std::min<long long>(std::max<long long>(1, (words + 255) / 256), 1024);
+    hipLaunchKernelGGL(popcount_rows, dim3((unsigned)blocks, (unsigned)rows), dim3(256), 0, s, bits, words, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_match(const KParams &P, int grid, bool with_av, hipStream_t s) {

@@ -46,10 +46,16 @@ struct KParams {
     int32_t mode;
     int32_t run_flags;
     int32_t batch_max_avg;     // leaf batching only while parents average at most this many candidates; 0 = always
+    uint32_t *mark;            // domains: per plan, a bitmap of mark_words words over rank ids (nullptr = off)
+    long long mark_words;
 };
 
 // with_av: the trie holds anti-vertex checks (selects the kernel variant)
 hipError_t launch_match(const KParams &P, int grid, bool with_av, hipStream_t s);
+
+// out[r] += number of set bits in row r of `rows` bitmaps of `words` words each
+hipError_t launch_popcount(const uint32_t *bits, long long words, int rows, unsigned long long *out,
+                           hipStream_t s);
 
 // resident wavefronts (one per workgroup) per compute unit for match_kernel
 int match_blocks_per_cu(bool with_av);

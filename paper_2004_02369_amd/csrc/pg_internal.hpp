@@ -60,6 +60,7 @@ struct Node {
     int32_t label0;    // root nodes: labels of level 0 and level 1
     int32_t label1;
     int8_t pv[kMaxLevels];  // emit: pattern vertex matched at each level
+    int32_t anchor_level;   // count: level holding the plan's anchored vertex (-1 none)
 };
 
 // A program: one matching order with its completion, as a sequence of levels.
@@ -81,6 +82,7 @@ struct Program {
 struct PlanImpl {
     pg_plan_info_t info{};
     int32_t k = 0;
+    int32_t anchor = -1;  // anchored regular vertex (domain plans), -1 none
     std::vector<Program> count_progs;  // merged, with multiplicities
     std::vector<Program> enum_progs;   // one per matching order, every vertex its own level
 };

@@ -220,10 +220,10 @@ void close_order(uint32_t lt[kMaxK], int k) {
 // member, and fix that vertex.  |Aut_t| is the product of the orbit sizes.
 // (Any choice breaks the symmetry exactly; this one reproduces the paper's
 // diamond example.)
-SymmetryBreak break_symmetries(const Typed &t) {
+SymmetryBreak break_symmetries(const Typed &t, uint32_t fixed0) {
     SymmetryBreak sb;
     AutSearch S(t);
-    uint32_t fixed = 0;
+    uint32_t fixed = fixed0;  // vertices every automorphism used must fix
     for (;;) {
         int orbit_of[kMaxK];
         for (int i = 0; i < t.k; i++) orbit_of[i] = -1;
@@ -285,14 +285,14 @@ bool covers(const Typed &t, uint32_t mask) {
 // Minimum vertex cover of true edges and anti-edges that is connected by
 // true edges (anti-vertices excluded).  Among minimum covers: most true
 // edges inside the core (fewer core matches), then the smallest vertex set.
-uint32_t min_connected_cover(const Typed &t) {
+uint32_t min_connected_cover(const Typed &t, uint32_t must) {
     const uint32_t full = (1u << t.k) - 1u;
     for (int s = 1; s <= t.k; s++) {
         uint32_t best = 0;
         int best_edges = -1;
         uint32_t m = (1u << s) - 1u;
         while (m <= full) {
-            if (covers(t, m) && connected_in(t, m)) {
+            if ((m & must) == must && covers(t, m) && connected_in(t, m)) {
                 int e = 0;
                 for (int i = 0; i < t.k; i++)
                     if (m >> i & 1u) e += popc(t.E[i] & m);
@@ -608,10 +608,14 @@ void add_programs(const Typed &t, const std::vector<int> &core_seq, uint32_t cor
     add_programs(t, core_seq, core, l2, emit, out, depth + 1);
 }
 
-std::string program_key(const Program &p) {
+std::string program_key(const Program &p, int anchor) {
     std::string s;
     auto put = [&](uint64_t v) { s.append(reinterpret_cast<const char *>(&v), sizeof(v)); };
     put(p.lev.size());
+    // anchored: programs that hold the anchor at different levels mark
+    // different vertices and must stay apart
+    for (size_t y = 0; anchor >= 0 && y < p.lev.size(); y++)
+        if (p.lev[y].pv == anchor) put(y);
     for (const Level &L : p.lev) {
         put(L.isect); put(L.diff); put(L.lo); put(L.hi); put(L.excl);
         put((uint64_t)(int64_t)L.label); put((uint64_t)L.group); put(L.avs.size());
@@ -641,8 +645,12 @@ pg_status compile_plan(const pg_pattern_desc *desc, const pg_plan_options *opt, 
     int mode = opt ? opt->mode : PG_PLAN_AUTO;
     if (mode < PG_PLAN_AUTO || mode > PG_PLAN_PARTIAL_ORDER) { *err = "unknown plan mode"; return PG_EINVAL; }
 
-    uint32_t core = min_connected_cover(t);
-    SymmetryBreak sb = break_symmetries(t);
+    const bool anchored = opt && opt->anchored;
+    if (opt && (opt->anchored < 0 || opt->anchored > 1)) { *err = "anchored must be 0 or 1"; return PG_EINVAL; }
+    if (anchored && (opt->anchor < 0 || opt->anchor >= t.k)) { *err = "anchor out of range"; return PG_EINVAL; }
+    const uint32_t must = anchored ? 1u << opt->anchor : 0u;
+    uint32_t core = min_connected_cover(t, must);
+    SymmetryBreak sb = break_symmetries(t, must);
 
     std::vector<std::vector<int>> les;
     std::vector<int> seq;
@@ -682,7 +690,7 @@ pg_status compile_plan(const pg_pattern_desc *desc, const pg_plan_options *opt, 
     // merge identical count programs (their counts are equal)
     std::map<std::string, size_t> idx;
     for (auto &p : cprogs) {
-        std::string key = program_key(p);
+        std::string key = program_key(p, anchored ? opt->anchor : -1);
         auto it = idx.find(key);
         if (it == idx.end()) {
             idx[key] = P.count_progs.size();
@@ -716,6 +724,8 @@ pg_status compile_plan(const pg_pattern_desc *desc, const pg_plan_options *opt, 
         I.orbit_vertex[i] = sb.orbit_vertex[i];
     }
     I.mode_used = mode_used;
+    I.anchor = anchored ? opt->anchor : -1;
+    P.anchor = I.anchor;
     I.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return PG_OK;
 }
@@ -741,6 +751,7 @@ std::string node_key(const Node &n, const std::vector<AVCheck> &avs) {
     if (n.kind == kCount || n.kind == kEmit) {
         put((uint64_t)n.plan);
         put(n.mult);
+        put((uint64_t)(int64_t)n.anchor_level);
         for (int i = 0; i < kMaxLevels; i++) put((uint64_t)(int64_t)n.pv[i]);
     }
     put(avs.size());
@@ -761,6 +772,7 @@ Node blank_node() {
     n.group = 1;
     n.mult = 1;
     for (int i = 0; i < kMaxLevels; i++) n.pv[i] = -1;
+    n.anchor_level = -1;
     return n;
 }
 
@@ -815,6 +827,8 @@ Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
                     h.n.mult = p.mult;
                     h.n.k = plans[pi]->k;
                     for (int y = 0; y <= F; y++) h.n.pv[y] = (int8_t)p.lev[y].pv;
+                    for (int y = 0; y < F; y++)
+                        if (plans[pi]->anchor >= 0 && p.lev[y].pv == plans[pi]->anchor) h.n.anchor_level = y;
                 }
                 h.key = node_key(h.n, h.avs);
                 cur = child(cur, std::move(h));

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "erdos_renyi_m", "chung_lu", "rmat", "gnp", "complete", "complete_multipartite",
     "cycle", "path", "star", "petersen", "turan", "disjoint_union", "dirty_copy",
-    "relabel", "all_graphs", "WORKLOADS", "workload",
+    "relabel", "all_graphs", "WORKLOADS", "workload", "labelled_workload",
 ]
 
 
@@ -244,7 +244,21 @@ WORKLOADS = {
     "rmat14_256k": dict(kind="rmat", scale=14, m=16 * (1 << 14), seed=20005),
     "rmat12_64k": dict(kind="rmat", scale=12, m=16 * (1 << 12), seed=20006),
     "chunglu_20k_100k": dict(kind="cl", n=20_000, m=100_000, gamma=2.1, w_max=700.0, seed=20007),
+    # labelled (frequent subgraph mining): power law, exponent 2.2, max weight
+    # 3.5 * sqrt(2m), 16 labels drawn uniformly with their own seed
+    "chunglu_1m_10m_l16": dict(kind="cl", n=1_000_000, m=10_000_000, gamma=2.2, w_max=15652.0, seed=20009,
+                               labels=16, label_seed=20010),
+    "chunglu_20k_100k_l4": dict(kind="cl", n=20_000, m=100_000, gamma=2.2, w_max=700.0, seed=20011,
+                                labels=4, label_seed=20012),
 }
+
+
+def labelled_workload(name: str):
+    """(n, src, dst, labels int16) of a labelled workload."""
+    w = WORKLOADS[name]
+    n, src, dst = workload(name)
+    labels = _rng(w["label_seed"]).integers(0, w["labels"], n).astype(np.int16)
+    return n, src, dst, labels
 
 
 def workload(name: str):

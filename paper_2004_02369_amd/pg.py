@@ -59,7 +59,8 @@ class pg_pattern_desc(ctypes.Structure):
 
 
 class pg_plan_options(ctypes.Structure):
-    _fields_ = [("mode", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("mode", ctypes.c_int32), ("anchored", ctypes.c_int32), ("anchor", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class pg_plan_info_t(ctypes.Structure):
@@ -68,7 +69,7 @@ class pg_plan_info_t(ctypes.Structure):
                 ("n_programs", ctypes.c_int32), ("n_levels", ctypes.c_int32), ("n_order", ctypes.c_int32),
                 ("order", ctypes.c_int32 * 240), ("n_orbit_steps", ctypes.c_int32),
                 ("orbit_size", ctypes.c_int32 * 16), ("orbit_vertex", ctypes.c_int32 * 16),
-                ("mode_used", ctypes.c_int32), ("plan_ms", ctypes.c_double)]
+                ("mode_used", ctypes.c_int32), ("plan_ms", ctypes.c_double), ("anchor", ctypes.c_int32)]
 
 
 class pg_run_config(ctypes.Structure):
@@ -87,7 +88,7 @@ MATCH_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes
 
 EXPORTS = ["pg_load_graph", "pg_graph_info", "pg_graph_csr", "pg_free_graph", "pg_plan_pattern",
            "pg_plan_pattern_ex", "pg_plan_info", "pg_free_plan", "pg_plan_programs", "pg_count", "pg_count_ex",
-           "pg_exists", "pg_enumerate", "pg_match", "pg_job_workspace_size", "pg_submit", "pg_job_poll",
+           "pg_exists", "pg_enumerate", "pg_match", "pg_domain_sizes", "pg_job_workspace_size", "pg_submit", "pg_job_poll",
            "pg_job_finish", "pg_last_error"]
 
 _lib = None
@@ -120,6 +121,8 @@ def lib():
     L.pg_exists.argtypes = [vp, vp, ctypes.POINTER(i32), vp]
     L.pg_enumerate.argtypes = [vp, vp, vp, u64, ctypes.POINTER(u64), vp]
     L.pg_match.argtypes = [vp, vp, MATCH_CB, vp, ctypes.POINTER(u64)]
+    L.pg_domain_sizes.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                  ctypes.POINTER(pg_run_config), vp]
     L.pg_job_workspace_size.argtypes = [vp, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(pg_run_config),
                                         ctypes.POINTER(u64)]
     L.pg_submit.argtypes = [vp, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(pg_run_config), vp, u64, vp,
@@ -223,6 +226,7 @@ class Plan:
         self._h = ctypes.c_void_p(handle)
         self.spec = spec
         self.k = int(spec["k"])
+        self.anchor = None
 
     def info(self) -> dict:
         i = pg_plan_info_t()
@@ -234,7 +238,7 @@ class Plan:
             "order": [(i.order[2 * j], i.order[2 * j + 1]) for j in range(i.n_order)],
             "orbit_size": list(i.orbit_size[: i.n_orbit_steps]),
             "orbit_vertex": list(i.orbit_vertex[: i.n_orbit_steps]),
-            "mode_used": i.mode_used, "plan_ms": i.plan_ms,
+            "mode_used": i.mode_used, "plan_ms": i.plan_ms, "anchor": i.anchor,
         }
 
     def programs(self, enum_mode: bool = False) -> list[dict]:
@@ -274,13 +278,17 @@ class Plan:
             pass
 
 
-def plan_pattern(spec, mode: int = PG_PLAN_AUTO) -> Plan:
+def plan_pattern(spec, mode: int = PG_PLAN_AUTO, anchor: int | None = None) -> Plan:
+    """Compile a pattern spec.  anchor: plan for the domain of that regular
+    vertex (domain_sizes)."""
     d, keep = pattern_desc(spec)
-    opt = pg_plan_options(mode=mode)
+    opt = pg_plan_options(mode=mode, anchored=0 if anchor is None else 1, anchor=0 if anchor is None else anchor)
     h = ctypes.c_void_p()
     _check(lib().pg_plan_pattern_ex(ctypes.byref(d), ctypes.byref(opt), ctypes.byref(h)))
     del keep
-    return Plan(h.value, spec)
+    p = Plan(h.value, spec)
+    p.anchor = anchor
+    return p
 
 
 # --------------------------------------------------------------- counting
@@ -319,6 +327,19 @@ def count(graph: Graph, plans, stream=None, **kw):
     single = isinstance(plans, Plan)
     res, _ = count_ex(graph, [plans] if single else plans, stream, **kw)
     return res[0] if single else res
+
+
+def domain_sizes(graph: Graph, plans, stream=None, **knobs):
+    """|dom(anchor)| of each anchored plan (MNI domains) and its counts, in
+    one launch."""
+    plans = list(plans)
+    arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    sizes = (ctypes.c_uint64 * len(plans))()
+    counts = (ctypes.c_uint64 * len(plans))()
+    cfg = run_config(**knobs)
+    _check(lib().pg_domain_sizes(graph._h, arr, len(plans), sizes, counts, ctypes.byref(cfg),
+                                 _stream_ptr(stream)))
+    return [int(x) for x in sizes], [int(x) for x in counts]
 
 
 def exists(graph: Graph, plan: Plan, stream=None) -> bool:

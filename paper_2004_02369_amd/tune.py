@@ -88,7 +88,8 @@ def fingerprint(G) -> str:
 
 
 def plan_key(plans) -> str:
-    return hashlib.sha256(json.dumps([p.spec for p in plans], sort_keys=True, default=list).encode()).hexdigest()[:24]
+    items = [p.spec if p.anchor is None else [p.spec, p.anchor] for p in plans]
+    return hashlib.sha256(json.dumps(items, sort_keys=True, default=list).encode()).hexdigest()[:24]
 
 
 # tuning records shipped with the package (written by autotune(cache_path=...))

@@ -239,3 +239,37 @@ def test_anti_vertex_with_true_edge_rejected():
     import ctypes
     h = ctypes.c_void_p()
     assert pg.lib().pg_plan_pattern(ctypes.byref(d), ctypes.byref(h)) == pg.PG_EINVAL
+
+
+ANCHOR_PATTERNS = [s for s in PLAN_PATTERNS if s["k"] <= 5]
+
+
+@pytest.mark.parametrize("pi", range(0, len(ANCHOR_PATTERNS), 2))
+def test_anchored_programs_reach_every_domain_vertex(pi, orc):
+    """An anchored plan (domains for MNI): its count programs count valid
+    maps / |stabiliser of the anchor| and its enumeration programs reach
+    every data vertex of the anchor's domain."""
+    spec = ANCHOR_PATTERNS[pi]
+    g = gg.gnp(9, 0.5, seed=300 + pi)
+    og = orc.Graph.from_tuple(g)
+    valid = orc.valid_maps(og, spec)
+    _, members = orc.domains(og, spec, members=True)
+    for u in range(spec["k"]):
+        plan = pg.plan_pattern(spec, anchor=u)
+        info = plan.info()
+        assert info["anchor"] == u and u in info["core"]
+        assert valid % info["aut"] == 0
+        assert interp_count(g, plan.programs()) == valid // info["aut"], (spec, u)
+        rows = interp_enumerate(g, plan.programs(enum_mode=True), spec["k"])
+        assert {r[u] for r in rows} == set(np.flatnonzero(members[u]).tolist()), (spec, u)
+
+
+def test_anchored_stabiliser_order():
+    # the anchor's stabiliser: K4 -> 3!, a 3-star's centre -> 3!, a leaf -> 2!
+    assert pg.plan_pattern(pt.clique(4), anchor=2).info()["aut"] == 6
+    star = pt.star(4)
+    assert pg.plan_pattern(star, anchor=0).info()["aut"] == 6
+    assert pg.plan_pattern(star, anchor=3).info()["aut"] == 2
+    assert pg.plan_pattern(pt.chain(4), anchor=0).info()["aut"] == 1
+    with pytest.raises(pg.PGError):
+        pg.plan_pattern(pt.clique(3), anchor=3)
