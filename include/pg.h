@@ -234,10 +234,28 @@ pg_status pg_enumerate(pg_graph *g, const pg_plan *plan, int32_t *out, uint64_t 
 /* Callback form of matching (Fig. "program examples", match(G, p, f)):
  * ids holds k original vertex ids indexed by pattern vertex.  A nonzero
  * return stops the exploration and the call returns PG_STOPPED.
- * n_matches receives the number of callbacks made.  Runs on the null
- * stream; the callback runs on the calling host thread. */
+ * n_matches receives the number of callbacks made.  Matches stream through
+ * one device buffer of about 64 MB: windows of root tasks are enumerated
+ * in turn and the callback sees each window's matches before the next
+ * window is launched, so a stop takes effect within one window.  Runs on
+ * the null stream; the callback runs on the calling host thread. */
 typedef int (*pg_match_cb)(const int32_t *ids, int32_t k, void *user);
 pg_status pg_match(pg_graph *g, const pg_plan *plan, pg_match_cb cb, void *user, uint64_t *n_matches);
+/* pg_match with the device buffer's capacity in rows (0 = about 64 MB). */
+pg_status pg_match_ex(pg_graph *g, const pg_plan *plan, pg_match_cb cb, void *user, uint64_t *n_matches,
+                      uint64_t buffer_rows);
+
+/* Root tasks of a plan's enumeration on a graph: every match is found from
+ * exactly one of them, so windows of tasks partition the matches.  Tasks
+ * are the graph's edges (each once, oriented by rank) when the plan's cores
+ * have two vertices or more, then the vertices when some core has one; the
+ * edges come costliest first. */
+pg_status pg_root_tasks(pg_graph *g, const pg_plan *plan, int64_t *n_tasks);
+
+/* pg_enumerate over the root tasks [task_begin, task_end) only (0 <=
+ * task_begin < task_end <= pg_root_tasks). */
+pg_status pg_enumerate_range(pg_graph *g, const pg_plan *plan, int64_t task_begin, int64_t task_end, int32_t *out,
+                             uint64_t cap, uint64_t *n_total, void *hip_stream);
 
 /* MNI domains (Sec. 2, frequent subgraph mining; Sec. 5.5): for each plan p,
  * compiled anchored at regular vertex u_p (pg_plan_options.anchored), the

@@ -490,6 +490,8 @@ struct LaunchArgs {
     int32_t *out = nullptr;
     uint64_t cap = 0;
     uint64_t *sizes = nullptr;     // domains: host, n_plans domain sizes (marks on)
+    int64_t task_begin = 0;        // root-task window; task_end 0 = all tasks
+    int64_t task_end = 0;
     uint32_t *mark_dev = nullptr;  // set by run(): the graph's mark bitmaps
     long long mark_words = 0;
 };
@@ -594,6 +596,8 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.batch_max_avg = cfg ? cfg->batch_max_avg : 0;
     P.mark = la.mark_dev;
     P.mark_words = la.mark_words;
+    P.task_begin = la.task_begin;
+    P.task_end = la.task_end;
     return P;
 }
 
@@ -641,6 +645,11 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     }
     LaunchPlan &L = g->launch;
     shape(g, cfg, L);  // the knobs may differ between calls
+    if (la.task_begin < 0 || la.task_end < 0 || (la.task_end > 0 && la.task_end <= la.task_begin) ||
+        la.task_end > L.n_et + L.n_vt || (la.task_end == 0 && la.task_begin > 0)) {
+        set_error("bad root-task window");
+        return PG_EINVAL;
+    }
 
     if (L.image.size() > g->trie_bytes) {
         dfree(g->trie_buf);
@@ -725,7 +734,7 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
         stats->total_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         stats->logical_bytes = ctl[kCtlBytes];
-        stats->root_tasks = (uint64_t)(L.n_et + L.n_vt);
+        stats->root_tasks = la.task_end > 0 ? (uint64_t)(la.task_end - la.task_begin) : (uint64_t)(L.n_et + L.n_vt);
         stats->grid_waves = L.grid;
         stats->chunk = L.chunk;
     }
@@ -822,41 +831,115 @@ pg_status pg_enumerate(pg_graph *g, const pg_plan *plan, int32_t *out, uint64_t 
     }
 }
 
+pg_status pg_root_tasks(pg_graph *g, const pg_plan *plan, int64_t *n_tasks) {
+    if (!g || !plan || !n_tasks) { set_error("NULL argument"); return PG_EINVAL; }
+    try {
+        std::vector<const pg::PlanImpl *> impls{&plan->impl};
+        const pg::Trie T = pg::build_trie(impls, true);
+        *n_tasks = (T.has_edge_root ? g->m : 0) + (T.has_vertex_root ? (int64_t)g->n : 0);
+        return PG_OK;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    }
+}
+
+pg_status pg_enumerate_range(pg_graph *g, const pg_plan *plan, int64_t task_begin, int64_t task_end, int32_t *out,
+                             uint64_t cap, uint64_t *n_total, void *hip_stream) {
+    if (!plan || !n_total) { set_error("NULL argument"); return PG_EINVAL; }
+    if (cap > 0 && !out) { set_error("out is NULL with cap > 0"); return PG_EINVAL; }
+    if (task_end <= task_begin || task_begin < 0) { set_error("bad root-task window"); return PG_EINVAL; }
+    LaunchArgs la;
+    la.mode = pg::kModeEmit;
+    la.out = out;
+    la.cap = cap;
+    la.task_begin = task_begin;
+    la.task_end = task_end;
+    const pg_plan *plans[1] = {plan};
+    try {
+        return run(g, plans, 1, nullptr, nullptr, nullptr, hip_stream, la, n_total);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    }
+}
+
+// Streams the matches through one device buffer: windows of root tasks are
+// enumerated one after another (every match is found from exactly one root
+// task), a window whose matches overflow the buffer is halved and redone,
+// and the callback sees each window's rows before the next launch.
 pg_status pg_match(pg_graph *g, const pg_plan *plan, pg_match_cb cb, void *user, uint64_t *n_matches) {
+    return pg_match_ex(g, plan, cb, user, n_matches, 0);
+}
+
+pg_status pg_match_ex(pg_graph *g, const pg_plan *plan, pg_match_cb cb, void *user, uint64_t *n_matches,
+                      uint64_t buffer_rows) {
     if (!g || !plan || !cb) { set_error("NULL argument"); return PG_EINVAL; }
     if (n_matches) *n_matches = 0;
-    uint64_t total = 0;
-    pg_status st = pg_enumerate(g, plan, nullptr, 0, &total, nullptr);
+    int64_t total = 0;
+    pg_status st = pg_root_tasks(g, plan, &total);
     if (st) return st;
     if (total == 0) return PG_OK;
     const int k = plan->impl.k;
     const uint64_t kMaxRows = (uint64_t)1 << 26;
-    if (total > kMaxRows) { set_error("too many matches for the callback form"); return PG_EUNSUPPORTED; }
+    uint64_t cap = buffer_rows ? buffer_rows
+                               : std::max<uint64_t>((uint64_t)1 << 16, ((uint64_t)64 << 20) / (4u * (uint64_t)k));
     DeviceGuard guard(g->device);
     int32_t *d = nullptr;
-    if (hipMalloc(reinterpret_cast<void **>(&d), total * (uint64_t)k * sizeof(int32_t)) != hipSuccess) {
-        set_error("hipMalloc match rows");
-        return PG_ENOMEM;
-    }
-    uint64_t got = 0;
-    st = pg_enumerate(g, plan, d, total, &got, nullptr);
+    auto grow = [&](uint64_t rows) -> pg_status {
+        dfree(d);
+        d = nullptr;
+        if (hipMalloc(reinterpret_cast<void **>(&d), rows * (uint64_t)k * sizeof(int32_t)) != hipSuccess) {
+            set_error("hipMalloc match rows");
+            return PG_ENOMEM;
+        }
+        cap = rows;
+        return PG_OK;
+    };
+    if ((st = grow(cap))) return st;
     std::vector<int32_t> h;
-    if (!st) {
-        h.resize(total * (uint64_t)k);
-        if (hipMemcpy(h.data(), d, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
+    int64_t begin = 0, width = total;
+    while (begin < total) {
+        const int64_t end = std::min(total, begin + width);
+        uint64_t got = 0;
+        st = pg_enumerate_range(g, plan, begin, end, d, cap, &got, nullptr);
+        if (st) break;
+        if (got > cap) {
+            if (end - begin > 1) {
+                // too many for the buffer: a narrower window, sized from this one
+                width = std::max<int64_t>(1, (int64_t)((double)(end - begin) * (double)cap / (2.0 * (double)got)));
+                continue;
+            }
+            if (got > kMaxRows) {
+                set_error("one root task yields more matches than the callback form buffers");
+                st = PG_EUNSUPPORTED;
+                break;
+            }
+            if ((st = grow(got))) break;
+            continue;
+        }
+        h.resize(got * (uint64_t)k);
+        if (got && hipMemcpy(h.data(), d, h.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
             set_error("copy of match rows failed");
             st = PG_EDEVICE;
+            break;
         }
+        bool stop = false;
+        for (uint64_t i = 0; i < got && !stop; i++) {
+            if (n_matches) (*n_matches)++;
+            if (cb(h.data() + i * (uint64_t)k, k, user)) stop = true;
+        }
+        if (stop) {
+            st = PG_STOPPED;
+            break;
+        }
+        begin = end;
+        // widen again while windows come back well under the buffer
+        if (got < cap / 4) width = std::min<int64_t>(total, width * 2);
     }
     dfree(d);
-    if (st) return st;
-    for (uint64_t i = 0; i < total; i++) {
-        if (n_matches) (*n_matches)++;
-        if (cb(h.data() + i * (uint64_t)k, k, user)) return PG_STOPPED;
-    }
-    return PG_OK;
+    return st;
 }
-
 
 // ----------------------------------------------------------- asynchronous jobs
 

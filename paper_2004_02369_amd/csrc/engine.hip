@@ -1154,7 +1154,11 @@ __device__ __forceinline__ void match_body(const KParams P) {
         }
     }
     wsync();
-    const long long total_tasks = P.n_etasks + P.n_vtasks;
+    // this launch's window of root tasks: [t_lo, t_hi) of the edge tasks
+    // followed by the vertex tasks
+    const long long t_lo = P.task_begin;
+    const long long t_hi = P.task_end > 0 ? P.task_end : P.n_etasks + P.n_vtasks;
+    const long long span = t_hi - t_lo;
     for (;;) {
         if (C.stopped()) break;
         // guided claiming: tasks are sorted costliest first, so the chunk
@@ -1164,13 +1168,13 @@ __device__ __forceinline__ void match_body(const KParams P) {
         long long chunk = 1;
         if (lane == 0) {
             const long long pos = (long long)__atomic_load_n(P.cursor, __ATOMIC_RELAXED);
-            chunk = 1 + (total_tasks > 0 ? (min(pos, total_tasks) * (long long)(P.chunk - 1)) / total_tasks : 0);
-            t0 = atomicAdd(P.cursor, (unsigned long long)chunk);
+            chunk = 1 + (span > 0 ? (min(pos, span) * (long long)(P.chunk - 1)) / span : 0);
+            t0 = (unsigned long long)t_lo + atomicAdd(P.cursor, (unsigned long long)chunk);
         }
         t0 = __shfl(t0, 0);
         chunk = __shfl(chunk, 0);
-        if ((long long)t0 >= total_tasks) break;
-        const long long c_end = min((long long)t0 + chunk, total_tasks);
+        if ((long long)t0 >= t_hi) break;
+        const long long c_end = min((long long)t0 + chunk, t_hi);
         for (long long tb = (long long)t0; tb < c_end;) {
             // edge tasks occupy [0, n_etasks), vertex tasks the rest; a chunk
             // may straddle the boundary

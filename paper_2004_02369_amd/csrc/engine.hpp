@@ -48,6 +48,8 @@ struct KParams {
     int32_t batch_max_avg;     // leaf batching only while parents average at most this many candidates; 0 = always
     uint32_t *mark;            // domains: per plan, a bitmap of mark_words words over rank ids (nullptr = off)
     long long mark_words;
+    long long task_begin;      // root tasks [task_begin, task_end) of this launch; task_end 0 = to the last
+    long long task_end;
 };
 
 // with_av: the trie holds anti-vertex checks (selects the kernel variant)

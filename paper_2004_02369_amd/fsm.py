@@ -176,9 +176,14 @@ def gpu_support(G, pg, batch: int = 64, log=None, **knobs):
 
     def support(cands):
         jobs = []  # (pattern index, plan)
+        order = []
         for i, p in enumerate(cands):
             for u in orbit_representatives(p):
-                jobs.append((i, pg.plan_pattern(p.spec(), anchor=u)))
+                order.append((p.labels[u], sorted(p.labels), p.k, i, u))
+        # plans whose roots carry the same labels share trie roots in a launch
+        order.sort()
+        for _, _, _, i, u in order:
+            jobs.append((i, pg.plan_pattern(cands[i].spec(), anchor=u)))
         best = [None] * len(cands)
         for s in range(0, len(jobs), batch):
             part = jobs[s:s + batch]

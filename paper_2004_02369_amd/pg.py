@@ -88,7 +88,7 @@ MATCH_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes
 
 EXPORTS = ["pg_load_graph", "pg_graph_info", "pg_graph_csr", "pg_free_graph", "pg_plan_pattern",
            "pg_plan_pattern_ex", "pg_plan_info", "pg_free_plan", "pg_plan_programs", "pg_count", "pg_count_ex",
-           "pg_exists", "pg_enumerate", "pg_match", "pg_domain_sizes", "pg_job_workspace_size", "pg_submit", "pg_job_poll",
+           "pg_exists", "pg_enumerate", "pg_match", "pg_match_ex", "pg_root_tasks", "pg_enumerate_range", "pg_domain_sizes", "pg_job_workspace_size", "pg_submit", "pg_job_poll",
            "pg_job_finish", "pg_last_error"]
 
 _lib = None
@@ -121,6 +121,9 @@ def lib():
     L.pg_exists.argtypes = [vp, vp, ctypes.POINTER(i32), vp]
     L.pg_enumerate.argtypes = [vp, vp, vp, u64, ctypes.POINTER(u64), vp]
     L.pg_match.argtypes = [vp, vp, MATCH_CB, vp, ctypes.POINTER(u64)]
+    L.pg_match_ex.argtypes = [vp, vp, MATCH_CB, vp, ctypes.POINTER(u64), u64]
+    L.pg_root_tasks.argtypes = [vp, vp, ctypes.POINTER(i64)]
+    L.pg_enumerate_range.argtypes = [vp, vp, i64, i64, vp, u64, ctypes.POINTER(u64), vp]
     L.pg_domain_sizes.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(u64), ctypes.POINTER(u64),
                                   ctypes.POINTER(pg_run_config), vp]
     L.pg_job_workspace_size.argtypes = [vp, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(pg_run_config),
@@ -364,14 +367,33 @@ def enumerate_matches(graph: Graph, plan: Plan, cap: int | None = None, stream=N
     return buf[:n].cpu().numpy(), int(tot.value)
 
 
-def match(graph: Graph, plan: Plan, fn) -> tuple[int, bool]:
+def root_tasks(graph: Graph, plan: Plan) -> int:
+    n = ctypes.c_int64()
+    _check(lib().pg_root_tasks(graph._h, plan._h, ctypes.byref(n)))
+    return int(n.value)
+
+
+def enumerate_range(graph: Graph, plan: Plan, task_begin: int, task_end: int, cap: int, stream=None):
+    """Matches found from root tasks [task_begin, task_end): (rows, total);
+    rows holds min(cap, total) of them."""
+    import torch
+    tot = ctypes.c_uint64()
+    buf = torch.empty((max(1, cap), plan.k), dtype=torch.int32, device=f"cuda:{graph.device}")
+    torch.cuda.synchronize(graph.device)
+    _check(lib().pg_enumerate_range(graph._h, plan._h, int(task_begin), int(task_end),
+                                    ctypes.c_void_p(buf.data_ptr()), cap, ctypes.byref(tot), _stream_ptr(stream)))
+    n = min(cap, int(tot.value))
+    return buf[:n].cpu().numpy(), int(tot.value)
+
+
+def match(graph: Graph, plan: Plan, fn, buffer_rows: int = 0) -> tuple[int, bool]:
     """Calls fn(ids: tuple) per match; a truthy return stops.  Returns
-    (callbacks made, stopped)."""
+    (callbacks made, stopped).  buffer_rows: device buffer (0 = default)."""
     def cb(ids, k, user):
         return 1 if fn(tuple(ids[i] for i in range(k))) else 0
     c = MATCH_CB(cb)
     n = ctypes.c_uint64()
-    st = _check(lib().pg_match(graph._h, plan._h, c, None, ctypes.byref(n)))
+    st = _check(lib().pg_match_ex(graph._h, plan._h, c, None, ctypes.byref(n), int(buffer_rows)))
     return int(n.value), st == PG_STOPPED
 
 
