@@ -262,12 +262,14 @@ pg_status pg_enumerate_range(pg_graph *g, const pg_plan *plan, int64_t task_begi
  * number of distinct data vertices v such that some valid map sends u_p to
  * v, i.e. |dom(u_p)| over all embeddings.  The MNI support of a pattern is
  * the minimum of |dom(u)| over its vertices; one anchor per automorphism
- * orbit suffices.  sizes: host, n_plans entries.  counts: host, n_plans
- * entries or NULL (valid maps / |stabiliser of the anchor|).  One launch
- * over all plans (at most 64); the graph holds n_plans n-bit bitmaps for it.
- * PG_EINVAL if a plan is not anchored.  Synchronous on hip_stream. */
+ * orbit suffices.  sizes: host, n_plans entries.  One launch over all
+ * plans (at most 64); the graph holds n_plans n-bit bitmaps for it.  Root
+ * tasks whose anchor image is already in the domain are skipped, so the
+ * launch counts nothing (pg_count of an anchored plan counts valid maps /
+ * |stabiliser of the anchor|).  PG_EINVAL if a plan is not anchored.
+ * Synchronous on hip_stream. */
 pg_status pg_domain_sizes(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *sizes,
-                          uint64_t *counts, const pg_run_config *cfg, void *hip_stream);
+                          const pg_run_config *cfg, void *hip_stream);
 
 /* ------------------------------------------------------ asynchronous jobs
  *

@@ -598,6 +598,9 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.mark_words = la.mark_words;
     P.task_begin = la.task_begin;
     P.task_end = la.task_end;
+    P.root_labels = 0;
+    for (int32_t r : L.trie.roots)
+        if (L.trie.nodes[r].label0 >= 0 || L.trie.nodes[r].label1 >= 0) P.root_labels = 1;
     return P;
 }
 
@@ -791,7 +794,7 @@ pg_status pg_exists(pg_graph *g, const pg_plan *plan, int32_t *found, void *hip_
 }
 
 pg_status pg_domain_sizes(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *sizes,
-                          uint64_t *counts, const pg_run_config *cfg, void *hip_stream) {
+                          const pg_run_config *cfg, void *hip_stream) {
     if (!sizes) { set_error("sizes is NULL"); return PG_EINVAL; }
     if (plans && n_plans > 0)
         for (int i = 0; i < n_plans && i < pg::kMaxPlansPerLaunch; i++)
@@ -809,8 +812,6 @@ pg_status pg_domain_sizes(pg_graph *g, const pg_plan *const *plans, int32_t n_pl
         set_error("host allocation failed");
         return PG_ENOMEM;
     }
-    if (counts)
-        for (int i = 0; i < n_plans; i++) counts[i] = c[i];
     return PG_OK;
 }
 

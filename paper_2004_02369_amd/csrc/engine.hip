@@ -192,11 +192,14 @@ struct Ctx {
     int plev0;      // levels taken from each prefix's parent slot (-1 none):
     int plev1;      //   root tasks give levels 0 and 1, set parents one level
     int amode;      // 1: the vl0 level's set is the arena slice of the prefix's parent
+    int anc_level;  // domains: the current root's anchor level (0 / 1, -1 none) and plan
+    int anc_plan;
     int32_t *arena; // this wave's arena for batched expansions
     unsigned long long acc;  // lane p: running count of plan p
 
     __device__ Ctx(const KParams &p, Lds &l, int32_t *b, int ln)
-        : P(p), L(l), buf0(b), lane(ln), vl0(-1), plev0(-1), plev1(-1), amode(0), arena(nullptr), acc(0) {}
+        : P(p), L(l), buf0(b), lane(ln), vl0(-1), plev0(-1), plev1(-1), amode(0), anc_level(-1), anc_plan(0),
+          arena(nullptr), acc(0) {}
 
     __device__ __forceinline__ int32_t *setbuf(int level) const { return buf0 + (long long)(level - 2) * P.set_cap; }
 
@@ -378,6 +381,14 @@ struct Ctx {
         const int32_t *sp0 = nullptr, *sp1 = nullptr, *sp2 = nullptr;
         int32_t sl0 = 0, sl1 = 0, sl2 = 0;
         int so0 = -1, so1 = -1, so2 = -1;  // segment owners (row owner, -1 = a set)
+        // domains: a prefix whose anchor image is already in the domain
+        // adds nothing
+        if (P.mark && N.anchor_level >= 0 && lane < np && L.pmode[lane] >= 0) {
+            const int32_t v = val(N.anchor_level, lane);
+            const uint32_t w =
+                __atomic_load_n(P.mark + (long long)N.plan * P.mark_words + (v >> 5), __ATOMIC_RELAXED);
+            if ((w >> (v & 31)) & 1u) L.pmode[lane] = -1;
+        }
         if (lane < np && L.pmode[lane] >= 0) {
             const int l = lane;
             int32_t lo = -1, hi = INT_MAX;
@@ -769,7 +780,14 @@ struct Ctx {
         const int32_t *my_bp = nullptr;  // this parent's base range (kept across rounds)
         int32_t my_bn = 0;
         int drv = -1;
-        const bool ok = lane < np && (okmask >> lane & 1ull);
+        bool ok = lane < np && (okmask >> lane & 1ull);
+        // domains: a parent whose anchor image is already in the domain adds nothing
+        if (ok && anc_level >= 0) {
+            const int32_t v = val(anc_level, lane);
+            const uint32_t w =
+                __atomic_load_n(P.mark + (long long)anc_plan * P.mark_words + (v >> 5), __ATOMIC_RELAXED);
+            ok = !((w >> (v & 31)) & 1u);
+        }
         if (ok) {
             int32_t lo = -1, hi = INT_MAX;
             for (uint32_t s = E.lo; s; s &= s - 1) lo = max(lo, val(__builtin_ctz(s), lane));
@@ -1109,15 +1127,27 @@ __device__ bool Ctx<kAV>::av_pass(const AVCheck &c, int x, int l, int32_t e) con
 }
 
 // Root checks (labels and anti-vertex checks on levels 0 / 1) for prefix l.
+// root filters that need only the task's vertices (u, v = -1 for a vertex
+// task's second slot): labels, and for domains a root whose anchor image is
+// already in the domain (another wave may have just set the bit: a stale
+// read only costs the work)
+__device__ __forceinline__ bool root_pre(const KParams &P, const Node &R, int32_t u, int32_t v) {
+    if (R.label0 >= 0 && (P.lab == nullptr || P.lab[u] != R.label0)) return false;
+    if (R.kind == kRootEdge && R.label1 >= 0 && (P.lab == nullptr || P.lab[v] != R.label1)) return false;
+    if (P.mark && R.anchor_level >= 0) {
+        const int32_t a = R.anchor_level == 0 ? u : v;
+        const uint32_t w = __atomic_load_n(P.mark + (long long)R.plan * P.mark_words + (a >> 5), __ATOMIC_RELAXED);
+        if ((w >> (a & 31)) & 1u) return false;
+    }
+    return true;
+}
+
+// anti-vertex checks of a root (the task's rows are loaded)
 template <bool kAV>
 __device__ __forceinline__ bool root_ok(Ctx<kAV> &C, const Node &R, int l) {
-    const KParams &P = C.P;
-    if (R.label0 >= 0 && (P.lab == nullptr || P.lab[C.L.tu[l]] != R.label0)) return false;
-    if (R.kind == kRootEdge && R.label1 >= 0 && (P.lab == nullptr || P.lab[C.L.tv[l]] != R.label1))
-        return false;
     if constexpr (kAV)
         for (int i = 0; i < R.av_count; i++) {
-            const AVCheck &c = P.avs[R.av_begin + i];
+            const AVCheck &c = C.P.avs[R.av_begin + i];
             // the deepest root level is the "candidate" of the check
             const int x = R.level;
             if (!C.av_pass(c, x, l, C.val(x, l))) return false;
@@ -1127,7 +1157,7 @@ __device__ __forceinline__ bool root_ok(Ctx<kAV> &C, const Node &R, int l) {
 
 // kAV: the trie holds anti-vertex checks (the variant without them keeps
 // the out-of-line check and its call frame out of the hot loops)
-template <bool kAV>
+template <bool kAV, bool kPre>
 __device__ __forceinline__ void match_body(const KParams P) {
     __shared__ Lds L;
     const int lane = threadIdx.x;
@@ -1185,16 +1215,25 @@ __device__ __forceinline__ void match_body(const KParams P) {
                 const int rid = uni(P.roots[r]);
                 const Node &R = P.nodes[rid];
                 if ((R.kind == kRootEdge) != edge_phase) continue;
-                // load the prefix batch: tasks tb .. tb + np
+                // the batch's tasks tb .. tb + np
+                int32_t u = 0, v = 0;
                 if (lane < np) {
                     const long long t = tb + lane;
-                    int32_t u, v = 0;
                     if (edge_phase) {
                         u = P.tsrc[t];
                         v = P.tdst[t];
                     } else {
                         u = P.n - 1 - (int32_t)(t - P.n_etasks);
                     }
+                }
+                bool okr = false;
+                if constexpr (kPre) {
+                    // labelled roots / domains: a root no task passes costs
+                    // no row loads
+                    okr = lane < np && root_pre(P, R, u, v);
+                    if (!__ballot(okr)) continue;
+                }
+                if (lane < np) {
                     L.tu[lane] = u;
                     L.tv[lane] = v;
                     L.tidx[lane] = 0;
@@ -1218,8 +1257,11 @@ __device__ __forceinline__ void match_body(const KParams P) {
                 C.plev0 = 0;
                 C.plev1 = edge_phase ? 1 : -1;
                 C.vl0 = -1;
-                bool okr = false;
-                if (lane < np) okr = root_ok(C, R, lane);
+                C.anc_level = P.mark ? uni(R.anchor_level) : -1;
+                C.anc_plan = uni(R.plan);
+                if constexpr (!kPre) okr = lane < np && root_pre(P, R, task_u, task_v);
+                if constexpr (kAV)
+                    if (okr) okr = root_ok(C, R, lane);
                 const unsigned long long okmask = __ballot(okr);
                 const int cb = uni(R.child_begin), cc = uni(R.child_count);
                 bool any_enum = false;
@@ -1276,10 +1318,15 @@ __device__ __forceinline__ void match_body(const KParams P) {
 
 // the common variant is held to 128 VGPRs: four wavefronts per SIMD
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) match_kernel(KParams P) {
-    match_body<false>(P);
+    match_body<false, false>(P);
 }
 
-__global__ void __launch_bounds__(64) match_kernel_av(KParams P) { match_body<true>(P); }
+// labelled roots or domain marks: roots are filtered before their rows load
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) match_kernel_pre(KParams P) {
+    match_body<false, true>(P);
+}
+
+__global__ void __launch_bounds__(64) match_kernel_av(KParams P) { match_body<true, true>(P); }
 
 int match_blocks_per_cu(bool with_av) {
     int nb = 0;
@@ -1311,6 +1358,7 @@ hipError_t launch_popcount(const uint32_t *bits, long long words, int rows, unsi
 
 hipError_t launch_match(const KParams &P, int grid, bool with_av, hipStream_t s) {
     if (with_av) hipLaunchKernelGGL(match_kernel_av, dim3(grid), dim3(64), 0, s, P);
+    else if (P.mark || P.root_labels) hipLaunchKernelGGL(match_kernel_pre, dim3(grid), dim3(64), 0, s, P);
     else hipLaunchKernelGGL(match_kernel, dim3(grid), dim3(64), 0, s, P);
     return hipGetLastError();
 }

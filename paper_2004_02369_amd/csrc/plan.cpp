@@ -359,7 +359,7 @@ bool seq_connected(const Typed &t, const std::vector<int> &seq) {
     return true;
 }
 
-std::vector<int> choose_sequence(const Typed &t, uint32_t core, const uint32_t lt[kMaxK]) {
+std::vector<int> choose_sequence(const Typed &t, uint32_t core, const uint32_t lt[kMaxK], int first = -1) {
     std::vector<int> verts;
     for (int i = 0; i < t.k; i++)
         if (core >> i & 1u) verts.push_back(i);
@@ -369,6 +369,8 @@ std::vector<int> choose_sequence(const Typed &t, uint32_t core, const uint32_t l
         std::vector<int> p = verts;
         do {
             if (!seq_connected(t, p)) continue;
+            // anchored: the anchor is one of the root vertices
+            if (first >= 0 && p[0] != first && !(p.size() > 1 && p[1] == first)) continue;
             long long s = sequence_score(t, p, lt);
             if (s > best_s) { best_s = s; best = p; }
         } while (std::next_permutation(p.begin(), p.end()));
@@ -385,6 +387,7 @@ std::vector<int> choose_sequence(const Typed &t, uint32_t core, const uint32_t l
             if (lt[u] >> v & 1u) minimal = false;
         if (minimal) { start = v; break; }
     }
+    if (first >= 0) start = first;
     seq.push_back(start);
     placed |= 1u << start;
     while (seq.size() < verts.size()) {
@@ -676,13 +679,13 @@ pg_status compile_plan(const pg_pattern_desc *desc, const pg_plan_options *opt, 
             std::memcpy(lt, sb.lt, sizeof(lt));
             for (size_t i = 0; i + 1 < L.size(); i++) lt[L[i]] |= 1u << L[i + 1];
             close_order(lt, t.k);
-            std::vector<int> cs = choose_sequence(t, core, lt);
+            std::vector<int> cs = choose_sequence(t, core, lt, anchored ? opt->anchor : -1);
             add_programs(t, cs, core, lt, false, cprogs);
             add_programs(t, cs, core, lt, true, eprogs);
         }
         n_mo = (int)mos.size();
     } else {
-        std::vector<int> cs = choose_sequence(t, core, sb.lt);
+        std::vector<int> cs = choose_sequence(t, core, sb.lt, anchored ? opt->anchor : -1);
         add_programs(t, cs, core, sb.lt, false, cprogs);
         add_programs(t, cs, core, sb.lt, true, eprogs);
         n_mo = 1;
@@ -748,7 +751,7 @@ std::string node_key(const Node &n, const std::vector<AVCheck> &avs) {
     put(n.excl); put(n.t_isect); put(n.t_diff); put((uint64_t)(int64_t)n.base);
     put((uint64_t)(int64_t)n.label); put((uint64_t)n.group); put((uint64_t)(int64_t)n.label0);
     put((uint64_t)(int64_t)n.label1);
-    if (n.kind == kCount || n.kind == kEmit) {
+    if (n.kind == kCount || n.kind == kEmit || n.anchor_level >= 0) {
         put((uint64_t)n.plan);
         put(n.mult);
         put((uint64_t)(int64_t)n.anchor_level);
@@ -806,6 +809,14 @@ Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
             r.n.level = F == 1 ? 0 : 1;
             r.n.label0 = p.lev[0].label;
             r.n.label1 = F == 1 ? -1 : p.lev[1].label;
+            // an anchored plan's root knows where its anchor is, so a root
+            // task whose anchor image is already in the domain is skipped
+            if (plans[pi]->anchor >= 0)
+                for (int y = 0; y <= r.n.level; y++)
+                    if (p.lev[y].pv == plans[pi]->anchor) {
+                        r.n.anchor_level = y;
+                        r.n.plan = (int32_t)pi;
+                    }
             for (int x = 0; x <= r.n.level; x++)
                 for (const AVCheck &c : p.lev[x].avs) r.avs.push_back(c);
             r.key = node_key(r.n, r.avs);

@@ -169,9 +169,14 @@ def mine(support_fn, alphabet, threshold: int, max_edges: int, log=None):
     return frequent_by_level, stats
 
 
-def gpu_support(G, pg, batch: int = 64, log=None, **knobs):
+class OutOfTime(RuntimeError):
+    pass
+
+
+def gpu_support(G, pg, batch: int = 64, log=None, deadline: float | None = None, **knobs):
     """support_fn running on libpg: one anchored plan per orbit
-    representative, batched across patterns, `batch` plans per launch."""
+    representative, batched across patterns, `batch` plans per launch.
+    deadline (time.perf_counter() value): raise OutOfTime when passed."""
     stats = {"launches": 0, "plans": 0, "kernel_s": 0.0}
 
     def support(cands):
@@ -185,15 +190,22 @@ def gpu_support(G, pg, batch: int = 64, log=None, **knobs):
         for _, _, _, i, u in order:
             jobs.append((i, pg.plan_pattern(cands[i].spec(), anchor=u)))
         best = [None] * len(cands)
+        t_log = time.perf_counter()
         for s in range(0, len(jobs), batch):
             part = jobs[s:s + batch]
             t0 = time.perf_counter()
-            sizes, _ = pg.domain_sizes(G, [pl for _, pl in part], **knobs)
+            sizes = pg.domain_sizes(G, [pl for _, pl in part], **knobs)
             stats["kernel_s"] += time.perf_counter() - t0
             stats["launches"] += 1
+            stats["plans"] += len(part)
+            if log and time.perf_counter() - t_log > 15:
+                log(f"  {s + len(part)}/{len(jobs)} anchored plans")
+                t_log = time.perf_counter()
+            if deadline is not None and time.perf_counter() > deadline:
+                stats["level_plans_done"], stats["level_plans"] = s + len(part), len(jobs)
+                raise OutOfTime(f"{s + len(part)} of {len(jobs)} anchored plans done")
             for (i, _), sz in zip(part, sizes):
                 best[i] = sz if best[i] is None else min(best[i], sz)
-        stats["plans"] += len(jobs)
         for _, pl in jobs:
             pl.free()
         return best
@@ -207,6 +219,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="chunglu_1m_10m_l16")
     ap.add_argument("--support", type=int, default=10000)
     ap.add_argument("--edges", type=int, default=3)
+    ap.add_argument("--budget-s", type=float, default=0.0, help="stop (and report progress) after this long")
     args = ap.parse_args(argv)
 
     import torch
@@ -223,12 +236,19 @@ def main(argv=None):
     t = time.perf_counter()
     G = pg.load_graph(n, src, dst, labels=labels, device=0)
     say(f"ingested n={G.n} m={G.m} d_max={G.d_max} in {time.perf_counter() - t:.1f} s")
-    support = gpu_support(G, pg)
     t = time.perf_counter()
-    freq, stats = mine(support, sorted(set(labels.tolist())), args.support, args.edges, log=say)
+    support = gpu_support(G, pg, log=say, deadline=t + args.budget_s if args.budget_s else None)
+    levels = []
+    try:
+        freq, stats = mine(support, sorted(set(labels.tolist())), args.support, args.edges,
+                           log=lambda m: (say(m), levels.append(m)))
+        finished = True
+    except OutOfTime as e:
+        say(f"time budget spent: {e}")
+        freq, stats, finished = {}, levels, False
     total = time.perf_counter() - t
     out = {"workload": args.workload, "n": G.n, "m": G.m, "d_max": G.d_max, "support": args.support,
-           "max_edges": args.edges, "seconds": total, "levels": stats, **support.stats,
+           "max_edges": args.edges, "seconds": total, "finished": finished, "levels": stats, **support.stats,
            "frequent": {str(e): len(f) for e, f in freq.items()}}
     print(json.dumps(out), flush=True)
     return 0

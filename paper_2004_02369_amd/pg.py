@@ -88,8 +88,9 @@ MATCH_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes
 
 EXPORTS = ["pg_load_graph", "pg_graph_info", "pg_graph_csr", "pg_free_graph", "pg_plan_pattern",
            "pg_plan_pattern_ex", "pg_plan_info", "pg_free_plan", "pg_plan_programs", "pg_count", "pg_count_ex",
-           "pg_exists", "pg_enumerate", "pg_match", "pg_match_ex", "pg_root_tasks", "pg_enumerate_range", "pg_domain_sizes", "pg_job_workspace_size", "pg_submit", "pg_job_poll",
-           "pg_job_finish", "pg_last_error"]
+           "pg_exists", "pg_enumerate", "pg_match", "pg_match_ex", "pg_root_tasks", "pg_enumerate_range",
+           "pg_domain_sizes", "pg_job_workspace_size", "pg_submit", "pg_job_poll", "pg_job_finish",
+           "pg_last_error"]
 
 _lib = None
 
@@ -124,8 +125,7 @@ def lib():
     L.pg_match_ex.argtypes = [vp, vp, MATCH_CB, vp, ctypes.POINTER(u64), u64]
     L.pg_root_tasks.argtypes = [vp, vp, ctypes.POINTER(i64)]
     L.pg_enumerate_range.argtypes = [vp, vp, i64, i64, vp, u64, ctypes.POINTER(u64), vp]
-    L.pg_domain_sizes.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(u64), ctypes.POINTER(u64),
-                                  ctypes.POINTER(pg_run_config), vp]
+    L.pg_domain_sizes.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(u64), ctypes.POINTER(pg_run_config), vp]
     L.pg_job_workspace_size.argtypes = [vp, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(pg_run_config),
                                         ctypes.POINTER(u64)]
     L.pg_submit.argtypes = [vp, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(pg_run_config), vp, u64, vp,
@@ -332,17 +332,14 @@ def count(graph: Graph, plans, stream=None, **kw):
     return res[0] if single else res
 
 
-def domain_sizes(graph: Graph, plans, stream=None, **knobs):
-    """|dom(anchor)| of each anchored plan (MNI domains) and its counts, in
-    one launch."""
+def domain_sizes(graph: Graph, plans, stream=None, **knobs) -> list[int]:
+    """|dom(anchor)| of each anchored plan (MNI domains), in one launch."""
     plans = list(plans)
     arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
     sizes = (ctypes.c_uint64 * len(plans))()
-    counts = (ctypes.c_uint64 * len(plans))()
     cfg = run_config(**knobs)
-    _check(lib().pg_domain_sizes(graph._h, arr, len(plans), sizes, counts, ctypes.byref(cfg),
-                                 _stream_ptr(stream)))
-    return [int(x) for x in sizes], [int(x) for x in counts]
+    _check(lib().pg_domain_sizes(graph._h, arr, len(plans), sizes, ctypes.byref(cfg), _stream_ptr(stream)))
+    return [int(x) for x in sizes]
 
 
 def exists(graph: Graph, plan: Plan, stream=None) -> bool:

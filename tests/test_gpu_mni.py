@@ -64,7 +64,7 @@ def test_domain_sizes_match_oracle(pg, case, knobs):
     say(f"{len(plans)} anchored plans, knobs {knobs}")
     got = {}
     for s in range(0, len(plans), 64):
-        sizes, counts = pg.domain_sizes(G, plans[s:s + 64], **knobs)
+        sizes = pg.domain_sizes(G, plans[s:s + 64], **knobs)
         for (i, u), sz in zip(jobs[s:s + 64], sizes):
             got[(i, u)] = sz
     for (i, u) in jobs:
@@ -78,7 +78,7 @@ def test_domain_counts_are_maps_over_stabiliser(pg, orc, case):
     for s in SPECS[:9]:
         valid = orc.valid_maps(og, s)
         plans = [pg.plan_pattern(s, anchor=u) for u in range(s["k"])]
-        _, counts = pg.domain_sizes(G, plans)
+        counts = pg.count(G, plans)
         for p, c in zip(plans, counts):
             assert c * p.info()["aut"] == valid, s
 
@@ -87,12 +87,10 @@ def test_special_graphs(pg):
     for n in (5, 9):
         G = pg.load_graph(*gg.complete(n), device=0)
         plans = [pg.plan_pattern(pt.clique(k), anchor=k - 1) for k in range(2, n + 2)]
-        sizes, _ = pg.domain_sizes(G, plans)
-        assert sizes == [n] * (n - 1) + [0]
+        assert pg.domain_sizes(G, plans) == [n] * (n - 1) + [0]
     G = pg.load_graph(*gg.star(7), device=0)
     star = pt.star(4)
-    sizes, _ = pg.domain_sizes(G, [pg.plan_pattern(star, anchor=u) for u in range(4)])
-    assert sizes == [1, 7, 7, 7]
+    assert pg.domain_sizes(G, [pg.plan_pattern(star, anchor=u) for u in range(4)]) == [1, 7, 7, 7]
     with pytest.raises(pg.PGError):
         pg.domain_sizes(G, [pg.plan_pattern(star)])
 

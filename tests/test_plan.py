@@ -260,6 +260,9 @@ def test_anchored_programs_reach_every_domain_vertex(pi, orc):
         assert info["anchor"] == u and u in info["core"]
         assert valid % info["aut"] == 0
         assert interp_count(g, plan.programs()) == valid // info["aut"], (spec, u)
+        # the anchor is a root vertex (level 0 or 1) of every program
+        for prog in plan.programs() + plan.programs(enum_mode=True):
+            assert u in [L["pv"] for L in prog["levels"][:2]], (spec, u)
         rows = interp_enumerate(g, plan.programs(enum_mode=True), spec["k"])
         assert {r[u] for r in rows} == set(np.flatnonzero(members[u]).tolist()), (spec, u)
 
