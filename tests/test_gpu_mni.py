@@ -106,3 +106,31 @@ def test_fsm_loop_gpu_equals_oracle(pg, orc):
         got, stats = fsm.mine(fsm.gpu_support(G, pg), [0, 1, 2], threshold, 3)
         assert got == ref
         assert sum(len(v) for v in got.values()) > 0
+
+
+def test_domains_at_labelled_workload_size(pg, orc):
+    """Full size of the labelled workload (Chung-Lu n = 10^6, 10^7 edges,
+    16 labels): domains of seeded random labelled 1- to 3-edge patterns,
+    every anchor, against the oracle."""
+    import random
+    n, src, dst, lab = gg.labelled_workload("chunglu_1m_10m_l16")
+    og = orc.Graph(n, src, dst, lab)
+    G = pg.load_graph(n, src, dst, labels=lab, device=0)
+    rng = random.Random(61)
+    shapes = [(2, [(0, 1)]), (3, [(0, 1), (1, 2)]), (3, [(0, 1), (1, 2), (0, 2)]),
+              (4, [(0, 1), (1, 2), (2, 3)]), (4, [(0, 1), (0, 2), (0, 3)])]
+    specs = []
+    for i in range(40):
+        k, edges = shapes[i % len(shapes)]
+        # few distinct labels per pattern, so symmetric cases occur too
+        pool = rng.sample(range(16), 2)
+        specs.append({"k": k, "edges": edges, "labels": [rng.choice(pool) for _ in range(k)]})
+    jobs = [(i, u) for i, s in enumerate(specs) for u in range(s["k"])]
+    plans = [pg.plan_pattern(specs[i], anchor=u) for i, u in jobs]
+    say(f"{len(plans)} anchored plans on chunglu_1m_10m_l16")
+    got = []
+    for s0 in range(0, len(plans), 64):
+        got += pg.domain_sizes(G, plans[s0:s0 + 64])
+    want = {i: orc.domains(og, s) for i, s in enumerate(specs)}
+    for (i, u), g_ in zip(jobs, got):
+        assert g_ == want[i][u], (specs[i], u)
