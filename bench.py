@@ -179,6 +179,19 @@ def main():
                 best = min(best, 1e3 * (time.perf_counter() - t1))
             single_ms.append(best)
 
+    # context: the same census by the inversion route (not the paper's
+    # method; the headline value above is the pattern-aware route)
+    from paper_2004_02369_amd import motifs
+    inv_ms = float("inf")
+    inv_counts = None
+    if not args.no_per_pattern:
+        for _ in range(2):
+            t1 = time.perf_counter()
+            inv = motifs.induced_counts(G, 4, pg, stream=stream)
+            inv_ms = min(inv_ms, 1e3 * (time.perf_counter() - t1))
+        order = [motifs.shapes(4).index(motifs._canon(4, s["edges"])) for s in specs]
+        inv_counts = [inv[i] for i in order]
+
     khash = kernel_source_hash()
     traffic = measured_traffic(khash)
     achieved = logical_bytes / (avg_kernel_ms * 1e-3) / 1e9
@@ -206,6 +219,7 @@ def main():
         "per_pattern_ms": single_ms or None,
         "per_pattern_ms_sum": sum(single_ms) if single_ms else None,
         "batched_speedup": sum(single_ms) / ms_per_step if single_ms else None,
+        "inversion_route": {"ms": inv_ms, "counts_equal": inv_counts == counts} if inv_counts else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "algorithmic_bytes_per_launch": logical_bytes, "kernel": "pg::match_kernel",

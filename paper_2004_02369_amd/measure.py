@@ -4,6 +4,7 @@
     python -m paper_2004_02369_amd.measure motifs5 --workload rmat12_64k
                                                      # 21 induced 5-motifs + K5, batched vs one launch each
     python -m paper_2004_02369_amd.measure small     # launch-bound case: ER 2k/20k, batched vs singles
+    python -m paper_2004_02369_amd.measure inversion # induced census via non-induced counts + inversion
 """
 from __future__ import annotations
 
@@ -63,6 +64,26 @@ def motifs5(args, pg, gg, pt):
                       "k5_equals_induced_k5": counts[-1] == counts[-2], "counts": counts}), flush=True)
 
 
+def inversion(args, pg, gg, pt):
+    """Induced motif census by the inversion route (edge-induced counts in
+    one launch, then exact inversion on the host) against the direct
+    pattern-aware route."""
+    from . import motifs
+    for wl, k in ((args.workload or "chunglu_100k_1m", 4), ("rmat12_64k", 5)):
+        G = pg.load_graph(*gg.workload(wl), device=0)
+        direct_plans = [pg.plan_pattern({"k": k, "edges": list(s), "induced": True}) for s in motifs.shapes(k)]
+        t0 = time.perf_counter()
+        direct = pg.count(G, direct_plans, time_limit_ms=args.limit_ms)
+        t_direct = time.perf_counter() - t0
+        best = float("inf")
+        for _ in range(3):
+            t0 = time.perf_counter()
+            inv = motifs.induced_counts(G, k, pg)
+            best = min(best, time.perf_counter() - t0)
+        print(json.dumps({"measure": "inversion", "workload": wl, "k": k, "direct_s": t_direct,
+                          "inversion_s": best, "speedup": t_direct / best, "equal": inv == direct}), flush=True)
+
+
 def small(args, pg, gg, pt):
     """Launch-bound regime: the six induced 4-motifs on ER 2k/20k, one
     batched launch against six launches, best of several repetitions."""
@@ -86,7 +107,7 @@ def small(args, pg, gg, pt):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["enum", "motifs5", "small"])
+    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion"])
     ap.add_argument("--workload", default=None)
     ap.add_argument("--limit-ms", type=int, default=600000)
     args = ap.parse_args(argv)
@@ -101,6 +122,8 @@ def main(argv=None):
     elif args.what == "motifs5":
         args.workload = args.workload or "rmat12_64k"
         motifs5(args, pg, gg, pt)
+    elif args.what == "inversion":
+        inversion(args, pg, gg, pt)
     else:
         small(args, pg, gg, pt)
     return 0
