@@ -113,7 +113,7 @@ struct pg_graph {
     size_t scratch_ints = 0;
     void *trie_buf = nullptr;
     size_t trie_bytes = 0;
-    unsigned long long *ctl = nullptr;  // counts[64], cursor, emit_ctr, bytes, flags[2]
+    unsigned long long *ctl = nullptr;  // control block: counts[64], cursor, emit counter, bytes, flags, start clock
     // cached launch preparation of the last pg_count / pg_enumerate call
     std::vector<uint64_t> trie_key;
     bool trie_emit = false;
