@@ -399,7 +399,31 @@ def catalogue(pg, pt):
             ("two_common_friends", "count", [pt.PA_TWO_COMMON_FRIENDS])]
     trees5 = [s for s in pt.all_edge_induced(4) if s["k"] == 5]
     ent += [(f"tree5_{i}", "count", [s]) for i, s in enumerate(trees5)]
-    return [Query(name, kind, [pg.plan_pattern(s) for s in specs]) for name, kind, specs in ent]
+    # one plan per typed pattern: entries that ask the same question (K4
+    # and the induced K4) share a plan, so their requests merge in a launch
+    plans = {}
+
+    def plan(spec):
+        key = pattern_key(spec)
+        if key not in plans:
+            plans[key] = pg.plan_pattern(spec)
+        return plans[key]
+    return [Query(name, kind, [plan(s) for s in specs]) for name, kind, specs in ent]
+
+
+def pattern_key(spec) -> str:
+    """The typed pattern a spec describes, written out: vertex count, true
+    edges, anti-edges (an induced spec's implied ones included), anti-vertex
+    neighbourhoods and labels.  Equal keys mean equal patterns."""
+    k = int(spec["k"])
+    edges = sorted(tuple(sorted(e)) for e in spec.get("edges", []))
+    anti = {tuple(sorted(e)) for e in spec.get("anti") or []}
+    if spec.get("induced"):
+        es = set(edges)
+        anti |= {(a, b) for a in range(k) for b in range(a + 1, k) if (a, b) not in es}
+    body = {"k": k, "edges": edges, "anti": sorted(anti), "av": [sorted(a) for a in spec.get("av") or []],
+            "labels": list(spec.get("labels") or []), "av_labels": list(spec.get("av_labels") or [])}
+    return json.dumps(body, sort_keys=True)
 
 
 def poisson_arrivals(lam: float, n: int, n_queries: int, seed: int):

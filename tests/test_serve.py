@@ -206,3 +206,11 @@ def test_policy_observe():
     assert pol.heavy(Request(0, _q("x", plans=[a, b, FakePlan("c")]), 0.0)) is False
     pol.est[id(b)] = 45.0
     assert pol.heavy(Request(0, _q("x", plans=[a, b]), 0.0)) is True
+
+
+def test_pattern_key_identifies_same_patterns():
+    from paper_2004_02369_amd import patterns as pt
+    k4 = pt.clique(4)
+    assert serve.pattern_key(k4) == serve.pattern_key(dict(k4, induced=True))
+    assert serve.pattern_key(pt.star(4)) != serve.pattern_key(pt.star(4, induced=True))
+    assert serve.pattern_key(pt.chain(3)) != serve.pattern_key(dict(pt.chain(3), labels=[0, 1, 0]))
