@@ -139,7 +139,7 @@ def main():
         res = None if args.retune else tune.lookup(G, plans, tune.RECORDS)
         if res is None:
             res = tune.autotune(G, plans, budget_s=args.tune_budget,
-                                cache_path=args.tune_out or None)
+                                cache_path=args.tune_out or None, force=args.retune)
         knobs = res["knobs"]
         tuning = {"record": bool(res.get("cached")), "default_kernel_ms": res["default_ms"],
                   "tuned_kernel_ms": res["ms"], "trials": len(res["trials"]),

@@ -590,31 +590,39 @@ struct Ctx {
         }
         if (lane == 0) L.seg_start[nseg] = total;
         wsync();
+        // lane t walks elements t, t + 64, ... of the concatenated segments;
+        // the element of the next pass is loaded before this pass's probes,
+        // so its load overlaps them
         int s = 0;  // this lane's segment, advanced monotonically
+        int32_t e_next = 0;
+        if (lane < total) {
+            // first visit: binary search for the segment holding the lane
+            int s_lo = 0, s_n = nseg;
+            while (s_n > 1) {
+                const int half = s_n >> 1;
+                if (L.seg_start[s_lo + half] <= lane) {
+                    s_lo += half;
+                    s_n -= half;
+                } else {
+                    s_n = half;
+                }
+            }
+            s = s_lo;
+            e_next = dec(L.seg_off[s])[lane - L.seg_start[s]];
+        }
         for (int32_t tb = 0; tb < total; tb += 64) {
             const int32_t t = tb + lane;
             bool ok = false;
             int l = 0;
-            int32_t e = 0;
+            const int32_t e = e_next;
+            const int s_cur = s;
+            if (t + 64 < total) {
+                while (L.seg_start[s + 1] <= t + 64) s++;
+                e_next = dec(L.seg_off[s])[t + 64 - L.seg_start[s]];
+            }
             if (t < total) {
-                if (tb == 0) {
-                    // first visit: binary search for the segment holding t
-                    int s_lo = 0, s_n = nseg;
-                    while (s_n > 1) {
-                        const int half = s_n >> 1;
-                        if (L.seg_start[s_lo + half] <= t) {
-                            s_lo += half;
-                            s_n -= half;
-                        } else {
-                            s_n = half;
-                        }
-                    }
-                    s = s_lo;
-                } else {
-                    while (L.seg_start[s + 1] <= t) s++;
-                }
+                const int s = s_cur;
                 l = L.seg_prefix[s];
-                e = dec(L.seg_off[s])[t - L.seg_start[s]];
                 if (L.pmode[l] == 0) {
                     ok = test_direct(N, x, l, L.pdrv[l], e, dec(L.boff[l]), L.blen[l]);
                 } else {
@@ -864,30 +872,36 @@ struct Ctx {
             if (lane == 0) L.seg_start[nseg] = total;
             wsync();
             int32_t out_n = 0;
+            // as in count_batch: the next pass's element loads before this
+            // pass's probes
             int s = 0;
+            int32_t e_next = 0;
+            if (lane < total) {
+                int s_lo = 0, s_n = nseg;
+                while (s_n > 1) {
+                    const int half = s_n >> 1;
+                    if (L.seg_start[s_lo + half] <= lane) {
+                        s_lo += half;
+                        s_n -= half;
+                    } else {
+                        s_n = half;
+                    }
+                }
+                s = s_lo;
+                e_next = dec(L.seg_off[s])[lane - L.seg_start[s]];
+            }
             for (int32_t tb = 0; tb < total; tb += 64) {
                 const int32_t t = tb + lane;
                 bool pass = false;
                 int l = 0;
-                int32_t e = 0;
+                const int32_t e = e_next;
+                const int s_cur = s;
+                if (t + 64 < total) {
+                    while (L.seg_start[s + 1] <= t + 64) s++;
+                    e_next = dec(L.seg_off[s])[t + 64 - L.seg_start[s]];
+                }
                 if (t < total) {
-                    if (tb == 0) {
-                        int s_lo = 0, s_n = nseg;
-                        while (s_n > 1) {
-                            const int half = s_n >> 1;
-                            if (L.seg_start[s_lo + half] <= t) {
-                                s_lo += half;
-                                s_n -= half;
-                            } else {
-                                s_n = half;
-                            }
-                        }
-                        s = s_lo;
-                    } else {
-                        while (L.seg_start[s + 1] <= t) s++;
-                    }
-                    l = L.seg_prefix[s];
-                    e = dec(L.seg_off[s])[t - L.seg_start[s]];
+                    l = L.seg_prefix[s_cur];
                     pass = test_direct(E, x, l, L.pdrv[l], e, dec(L.boff[l]), L.blen[l]);
                 }
                 const unsigned long long bal = __ballot(pass);

@@ -112,11 +112,11 @@ def default_cache_path() -> str:
 
 
 def autotune(G, plans, reps: int = 2, rounds: int = 2, budget_s: float = 60.0, cache_path: str | None = None,
-             log=None):
+             log=None, force: bool = False):
     """Tune the launch knobs of `plans` on graph G.  Returns a dict with the
     best knobs, their time, the default's time and every trial.  With
     cache_path, a cached result for the same graph and plans is returned
-    without measuring, and a new one is stored."""
+    without measuring (unless force), and a new one is stored."""
     from . import pg
     plans = list(plans)
     key = f"{fingerprint(G)}:{plan_key(plans)}"
@@ -124,7 +124,7 @@ def autotune(G, plans, reps: int = 2, rounds: int = 2, budget_s: float = 60.0, c
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
-        if key in cache:
+        if key in cache and not force:
             return dict(cache[key], cached=True)
 
     def measure(knobs, limit_ms):
