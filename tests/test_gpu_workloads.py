@@ -58,6 +58,13 @@ def test_chunglu_100k_1m_six_motifs_batched(pg, orc):
     plans = [pg.plan_pattern(s) for s in specs]
     want = _motif_expect(orc, w["induced4"], 4, specs)
     assert pg.count(G, plans) == want
+    # the launch configuration the benchmark times: the committed tuning record
+    from paper_2004_02369_amd import tune
+    rec = tune.lookup(G, plans, tune.RECORDS)
+    assert rec is not None, "no tuning record for this graph and plan set"
+    knobs = {k: v for k, v in rec["knobs"].items() if v}
+    say(f"chunglu_100k_1m with the benchmark's knobs {knobs}")
+    assert pg.count(G, plans, **knobs) == want
     say("chunglu_100k_1m triangle / wedge")
     assert pg.count(G, [pg.plan_pattern(pt.clique(3)), pg.plan_pattern(pt.star(3))]) == \
         [w["triangle"], w["sum_c_d_2"]]
