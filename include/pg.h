@@ -168,11 +168,17 @@ void pg_free_plan(pg_plan *plan);
  * multiplicities); 1: the enumeration programs.  buf: host, cap int32
  * entries; *len receives the number of entries needed (PG_EINVAL with
  * *len set when cap is too small).  Layout: n_programs, then per program
- *   n_levels, mult_lo, mult_hi, and per level
+ *   n_levels, mult_lo, mult_hi, n_levels levels, n_factors, n_factors levels,
+ * each level being
  *   isect diff lo hi excl t_isect t_diff base label group pv n_av,
  *   then per anti-vertex check: nbr label xmask[16].
  * Level masks are over earlier levels (bit y = level y); pv is the pattern
- * vertex matched at the level; the last level counts C(|S|, group). */
+ * vertex matched at the level; the last level counts C(|S|, group).
+ * Factors (count programs only) are further non-core groups evaluated at
+ * the last level's depth, each independent of every other non-core vertex
+ * (a label none of them can carry, no order relation or anti-vertex between
+ * them): a prefix's count is the product of every factor's C(|S|, group)
+ * and the last level's (Sec. 4, non-core vertices counted from set sizes). */
 pg_status pg_plan_programs(const pg_plan *plan, int32_t enum_mode, int32_t *buf, int64_t cap, int64_t *len);
 
 /* ---------------------------------------------------------------- counting */

@@ -461,7 +461,7 @@ pg_status pg_plan_programs(const pg_plan *plan, int32_t enum_mode, int32_t *buf,
         v.push_back((int32_t)p.lev.size());
         v.push_back((int32_t)(uint32_t)(p.mult & 0xFFFFFFFFu));
         v.push_back((int32_t)(uint32_t)(p.mult >> 32));
-        for (const pg::Level &L : p.lev) {
+        auto put = [&](const pg::Level &L) {
             for (uint32_t x : {L.isect, L.diff, L.lo, L.hi, L.excl, L.t_isect, L.t_diff}) v.push_back((int32_t)x);
             v.push_back(L.base);
             v.push_back(L.label);
@@ -473,7 +473,10 @@ pg_status pg_plan_programs(const pg_plan *plan, int32_t enum_mode, int32_t *buf,
                 v.push_back(c.label);
                 for (int i = 0; i < pg::kMaxLevels; i++) v.push_back((int32_t)c.xmask[i]);
             }
-        }
+        };
+        for (const pg::Level &L : p.lev) put(L);
+        v.push_back((int32_t)p.factors.size());
+        for (const pg::Level &L : p.factors) put(L);
     }
     *len = (int64_t)v.size();
     if (!buf || cap < (int64_t)v.size()) { set_error("buffer too small"); return PG_EINVAL; }
@@ -601,6 +604,9 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.root_labels = 0;
     for (int32_t r : L.trie.roots)
         if (L.trie.nodes[r].label0 >= 0 || L.trie.nodes[r].label1 >= 0) P.root_labels = 1;
+    P.factors = 0;
+    for (const pg::Node &n : L.trie.nodes)
+        if (n.kind == pg::kFactor) P.factors = 1;
     return P;
 }
 

@@ -182,7 +182,13 @@ __device__ __forceinline__ bool in_range(const KParams &P, const int32_t *p, int
     return contains(p, n, e);
 }
 
-template <bool kAV>
+// Products of independent groups, prefix p: the factor nodes' product so
+// far (1 between products).  Only the variant that evaluates factor nodes
+// references it, so only that kernel allocates it.
+__shared__ unsigned long long fac_lds[kP];
+
+// kFac: the trie may hold kFactor nodes
+template <bool kAV, bool kFac>
 struct Ctx {
     const KParams P;  // by value: a reference to the kernel argument would force a private copy
     Lds &L;
@@ -389,6 +395,9 @@ struct Ctx {
                 __atomic_load_n(P.mark + (long long)N.plan * P.mark_words + (v >> 5), __ATOMIC_RELAXED);
             if ((w >> (v & 31)) & 1u) L.pmode[lane] = -1;
         }
+        // products: a prefix with an empty factor set adds nothing
+        if constexpr (kFac)
+            if (lane < np && fac_lds[lane] == 0) L.pmode[lane] = -1;
         if (lane < np && L.pmode[lane] >= 0) {
             const int l = lane;
             int32_t lo = -1, hi = INT_MAX;
@@ -654,36 +663,51 @@ struct Ctx {
         if (!emit) {
             unsigned long long contrib = 0;
             bool ovf = false;
+            // a factor node only multiplies into its prefix's product; the
+            // count node after it closes the product
+            const bool factor = kFac && N.kind == kFactor;
             if (lane < np && L.pmode[lane] >= 0) {
                 const unsigned long long c = L.pmode[lane] == 0
                                                  ? (unsigned long long)L.pcnt[lane]
                                                  : (unsigned long long)(L.pconst[lane] - (int32_t)L.pcnt[lane]);
                 contrib = choose(c, N.group, &ovf);
-                // domains: this prefix has a match, so its anchor's image is in
-                // the anchor's domain
-                if (P.mark && contrib && N.anchor_level >= 0) {
-                    const int32_t v = val(N.anchor_level, lane);
-                    atomicOr(P.mark + (long long)N.plan * P.mark_words + (v >> 5), 1u << (v & 31));
+                if constexpr (kFac) {
+                    unsigned long long q;
+                    if (__builtin_mul_overflow(contrib, fac_lds[lane], &q)) ovf = true;
+                    contrib = q;
                 }
-                unsigned long long q;
-                if (__builtin_mul_overflow(contrib, N.mult, &q)) ovf = true;
-                contrib = q;
+                if (!factor) {
+                    // domains: this prefix has a match, so its anchor's image
+                    // is in the anchor's domain
+                    if (P.mark && contrib && N.anchor_level >= 0) {
+                        const int32_t v = val(N.anchor_level, lane);
+                        atomicOr(P.mark + (long long)N.plan * P.mark_words + (v >> 5), 1u << (v & 31));
+                    }
+                    unsigned long long q;
+                    if (__builtin_mul_overflow(contrib, N.mult, &q)) ovf = true;
+                    contrib = q;
+                }
             }
-            for (int off = 32; off > 0; off >>= 1) {
-                const unsigned long long o = __shfl_xor(contrib, off);
-                const unsigned long long s = contrib + o;
-                if (s < contrib) ovf = true;
-                contrib = s;
-            }
-            if (__ballot(ovf) && lane == 0) atomicOr(P.flags, 1);
-            // every lane holds the batch total; lane N.plan keeps that plan's sum
-            if (lane == N.plan) {
-                const unsigned long long s = acc + contrib;
-                if (s < acc) atomicOr(P.flags, 1);
-                acc = s;
-                if (P.mode == kModeExists && s > 0) {
-                    atomicOr(P.flags + 1, 1);
-                    L.stop = 1;
+            if constexpr (kFac) fac_lds[lane] = factor ? contrib : 1ull;
+            if (factor) {
+                if (__ballot(ovf) && lane == 0) atomicOr(P.flags, 1);
+            } else {
+                for (int off = 32; off > 0; off >>= 1) {
+                    const unsigned long long o = __shfl_xor(contrib, off);
+                    const unsigned long long s = contrib + o;
+                    if (s < contrib) ovf = true;
+                    contrib = s;
+                }
+                if (__ballot(ovf) && lane == 0) atomicOr(P.flags, 1);
+                // every lane holds the batch total; lane N.plan keeps that plan's sum
+                if (lane == N.plan) {
+                    const unsigned long long s = acc + contrib;
+                    if (s < acc) atomicOr(P.flags, 1);
+                    acc = s;
+                    if (P.mode == kModeExists && s > 0) {
+                        atomicOr(P.flags + 1, 1);
+                        L.stop = 1;
+                    }
                 }
             }
         }
@@ -1133,8 +1157,8 @@ __device__ __noinline__ bool av_check(const KParams &P, const int32_t *vals, con
 
 // every level value comes from Ctx::val, which knows the batch layout
 // (fixed assignment, root batch, set batch or task batch)
-template <bool kAV>
-__device__ bool Ctx<kAV>::av_pass(const AVCheck &c, int x, int l, int32_t e) const {
+template <bool kAV, bool kFac>
+__device__ bool Ctx<kAV, kFac>::av_pass(const AVCheck &c, int x, int l, int32_t e) const {
     int32_t vals[kMaxLevels];
     for (int y = 0; y < kMaxLevels; y++) vals[y] = y < x ? val(y, l) : (y == x ? e : 0);
     return av_check(P, vals, c);
@@ -1157,8 +1181,8 @@ __device__ __forceinline__ bool root_pre(const KParams &P, const Node &R, int32_
 }
 
 // anti-vertex checks of a root (the task's rows are loaded)
-template <bool kAV>
-__device__ __forceinline__ bool root_ok(Ctx<kAV> &C, const Node &R, int l) {
+template <bool kAV, bool kFac>
+__device__ __forceinline__ bool root_ok(Ctx<kAV, kFac> &C, const Node &R, int l) {
     if constexpr (kAV)
         for (int i = 0; i < R.av_count; i++) {
             const AVCheck &c = C.P.avs[R.av_begin + i];
@@ -1176,7 +1200,7 @@ __device__ __forceinline__ void match_body(const KParams P) {
     __shared__ Lds L;
     const int lane = threadIdx.x;
     int32_t *buf0 = P.scratch ? P.scratch + (long long)blockIdx.x * P.wave_stride : nullptr;
-    Ctx<kAV> C(P, L, buf0, lane);
+    Ctx<kAV, kPre> C(P, L, buf0, lane);
     C.arena = buf0 ? buf0 + P.wave_stride - P.arena_cap : nullptr;
     if (lane < kMaxLevels) {
         // a valid vertex in every slot of the fixed assignment
@@ -1187,6 +1211,7 @@ __device__ __forceinline__ void match_body(const KParams P) {
         L.cur_idx[lane] = 0;
         L.set_len[lane] = 0;
     }
+    if constexpr (kPre) fac_lds[lane] = 1;
     if (lane == 0) {
         L.stop = 0;
         L.bytes = 0;
@@ -1335,7 +1360,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ma
     match_body<false, false>(P);
 }
 
-// labelled roots or domain marks: roots are filtered before their rows load
+// labelled roots or domain marks: roots are filtered before their rows load;
+// also the variant that evaluates factor nodes
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) match_kernel_pre(KParams P) {
     match_body<false, true>(P);
 }
@@ -1372,7 +1398,8 @@ hipError_t launch_popcount(const uint32_t *bits, long long words, int rows, unsi
 
 hipError_t launch_match(const KParams &P, int grid, bool with_av, hipStream_t s) {
     if (with_av) hipLaunchKernelGGL(match_kernel_av, dim3(grid), dim3(64), 0, s, P);
-    else if (P.mark || P.root_labels) hipLaunchKernelGGL(match_kernel_pre, dim3(grid), dim3(64), 0, s, P);
+    else if (P.mark || P.root_labels || P.factors)
+        hipLaunchKernelGGL(match_kernel_pre, dim3(grid), dim3(64), 0, s, P);
     else hipLaunchKernelGGL(match_kernel, dim3(grid), dim3(64), 0, s, P);
     return hipGetLastError();
 }

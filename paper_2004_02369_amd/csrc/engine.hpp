@@ -51,6 +51,7 @@ struct KParams {
     long long task_begin;      // root tasks [task_begin, task_end) of this launch; task_end 0 = to the last
     long long task_end;
     int32_t root_labels;       // some root node has a label (roots are then filtered before loading rows)
+    int32_t factors;           // the trie holds kFactor nodes (selects a variant that evaluates them)
 };
 
 // with_av: the trie holds anti-vertex checks (selects the kernel variant)

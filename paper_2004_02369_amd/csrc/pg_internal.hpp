@@ -24,6 +24,7 @@ enum NodeKind : int32_t {
     kEnum = 2,        // materialise this level's candidate set, then descend per candidate
     kCount = 3,       // add C(|candidates|, group) * mult to counts[plan]
     kEmit = 4,        // write one match row per candidate
+    kFactor = 5,      // C(|candidates|, group) multiplies the next count sibling's term
 };
 
 // Anti-vertex constraint (Sec. 3.1.2 / Sec. 4.3), evaluated for a candidate
@@ -76,6 +77,12 @@ struct Level {
 
 struct Program {
     std::vector<Level> lev;    // last level is the count / emit level
+    // count programs: further non-core groups, each independent of every
+    // other non-core vertex (its own fixed label, no order relation to
+    // them, no anti-vertex), counted at the last level's depth; the
+    // program's count per prefix is the product of their C(|S|, j) and
+    // the last level's
+    std::vector<Level> factors;
     uint64_t mult = 1;
 };
 

@@ -504,6 +504,38 @@ BuiltProgram build_program(const Typed &t, const std::vector<int> &core_seq, uin
         if (ca != cb) return ca > cb;
         return xa < xb;
     });
+    // Count programs: a group whose fixed label no other non-core vertex
+    // can carry, with no anti-vertex and no order relation to another
+    // non-core vertex beyond what the core's order implies, never shares an
+    // image with the other non-core vertices, so its C(|S|, j) multiplies
+    // the rest instead of being enumerated (the set-size counting of
+    // non-core vertices, Sec. 4, applied to each independent group)
+    std::vector<int> fac_groups;
+    if (!emit) {
+        const uint32_t noncore = ((1u << t.k) - 1u) & ~core;
+        auto implied = [&](int a, int b) {  // a < b follows from a < c < b, c in the core
+            for (int c = 0; c < t.k; c++)
+                if ((core >> c & 1u) && (lt[a] >> c & 1u) && (lt[c] >> b & 1u)) return true;
+            return false;
+        };
+        std::vector<int> keep;
+        for (int g : order_groups) {
+            uint32_t gm = 0;
+            for (int x : groups[g]) gm |= 1u << x;
+            const int lab = t.lab[groups[g][0]];
+            bool ok = lab >= 0 && !(gm & inv);
+            for (int y = 0; ok && y < t.k; y++) {
+                if (!(noncore >> y & 1u) || (gm >> y & 1u)) continue;
+                if (t.lab[y] < 0 || t.lab[y] == lab) ok = false;
+                for (int x : groups[g]) {
+                    if ((lt[x] >> y & 1u) && !implied(x, y)) ok = false;
+                    if ((lt[y] >> x & 1u) && !implied(y, x)) ok = false;
+                }
+            }
+            (ok ? fac_groups : keep).push_back(g);
+        }
+        order_groups.swap(keep);
+    }
     std::vector<int> seq = core_seq;
     for (int g : order_groups)
         for (int x : groups[g]) seq.push_back(x);
@@ -524,10 +556,9 @@ BuiltProgram build_program(const Typed &t, const std::vector<int> &core_seq, uin
     int level_of[kMaxK];
     for (int i = 0; i < kMaxK; i++) level_of[i] = -1;
     for (int x = 0; x <= F; x++) level_of[seq[x]] = x;
-    bp.prog.lev.resize(F + 1);
-    for (int x = 0; x <= F; x++) {
-        Level &L = bp.prog.lev[x];
-        int u = seq[x];
+    // pattern vertex u matched at level x, against the images of levels < x
+    auto make_level = [&](int u, int x, int group) {
+        Level L;
         for (int y = 0; y < x; y++) {
             int w = seq[y];
             uint32_t bit = 1u << y;
@@ -539,8 +570,12 @@ BuiltProgram build_program(const Typed &t, const std::vector<int> &core_seq, uin
         L.excl = ((1u << x) - 1u) & ~(L.isect | L.lo | L.hi);
         L.label = t.lab[u];
         L.pv = u;
-        L.group = (x == F) ? jgroup : 1;
-    }
+        L.group = group;
+        return L;
+    };
+    bp.prog.lev.resize(F + 1);
+    for (int x = 0; x <= F; x++) bp.prog.lev[x] = make_level(seq[x], x, x == F ? jgroup : 1);
+    for (int g : fac_groups) bp.prog.factors.push_back(make_level(groups[g][0], F, (int)groups[g].size()));
     // anti-vertex checks: evaluated at the deepest level they depend on
     for (int a = 0; a < t.nav; a++) {
         uint32_t deps = t.AV[a];
@@ -563,8 +598,7 @@ BuiltProgram build_program(const Typed &t, const std::vector<int> &core_seq, uin
     }
     // base sets: a materialised earlier level (>= 2, below the final level's
     // parent chain) whose candidates contain every candidate of this level
-    for (int x = 2; x <= F; x++) {
-        Level &L = bp.prog.lev[x];
+    auto pick_base = [&](Level &L, int x) {
         int best = -1, best_cov = -1;
         for (int b = 2; b < x; b++) {
             const Level &B = bp.prog.lev[b];
@@ -582,7 +616,9 @@ BuiltProgram build_program(const Typed &t, const std::vector<int> &core_seq, uin
             L.t_isect = L.isect;
             L.t_diff = L.diff;
         }
-    }
+    };
+    for (int x = 2; x <= F; x++) pick_base(bp.prog.lev[x], x);
+    for (Level &L : bp.prog.factors) pick_base(L, F);
     for (int x = 0; x < 2 && x <= F; x++) {
         bp.prog.lev[x].t_isect = bp.prog.lev[x].isect;
         bp.prog.lev[x].t_diff = bp.prog.lev[x].diff;
@@ -619,14 +655,16 @@ std::string program_key(const Program &p, int anchor) {
     // different vertices and must stay apart
     for (size_t y = 0; anchor >= 0 && y < p.lev.size(); y++)
         if (p.lev[y].pv == anchor) put(y);
-    for (const Level &L : p.lev) {
-        put(L.isect); put(L.diff); put(L.lo); put(L.hi); put(L.excl);
-        put((uint64_t)(int64_t)L.label); put((uint64_t)L.group); put(L.avs.size());
-        for (const AVCheck &c : L.avs) {
-            put(c.nbr); put((uint64_t)(int64_t)c.label);
-            for (int i = 0; i < kMaxLevels; i++) put(c.xmask[i]);
+    put(p.factors.size());
+    for (const std::vector<Level> *ls : {&p.lev, &p.factors})
+        for (const Level &L : *ls) {
+            put(L.isect); put(L.diff); put(L.lo); put(L.hi); put(L.excl);
+            put((uint64_t)(int64_t)L.label); put((uint64_t)L.group); put(L.avs.size());
+            for (const AVCheck &c : L.avs) {
+                put(c.nbr); put((uint64_t)(int64_t)c.label);
+                for (int i = 0; i < kMaxLevels; i++) put(c.xmask[i]);
+            }
         }
-    }
     return s;
 }
 
@@ -751,7 +789,7 @@ std::string node_key(const Node &n, const std::vector<AVCheck> &avs) {
     put(n.excl); put(n.t_isect); put(n.t_diff); put((uint64_t)(int64_t)n.base);
     put((uint64_t)(int64_t)n.label); put((uint64_t)n.group); put((uint64_t)(int64_t)n.label0);
     put((uint64_t)(int64_t)n.label1);
-    if (n.kind == kCount || n.kind == kEmit || n.anchor_level >= 0) {
+    if (n.kind == kCount || n.kind == kEmit || n.kind == kFactor || n.anchor_level >= 0) {
         put((uint64_t)n.plan);
         put(n.mult);
         put((uint64_t)(int64_t)n.anchor_level);
@@ -822,27 +860,45 @@ Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
             r.key = node_key(r.n, r.avs);
             int cur = child(-1, std::move(r));
             n_programs++;
-            for (int x = H[cur].n.level + 1; x <= F; x++) {
-                const Level &L = p.lev[x];
+            int anchor_level = -1;
+            for (int y = 0; y < F; y++)
+                if (plans[pi]->anchor >= 0 && p.lev[y].pv == plans[pi]->anchor) anchor_level = y;
+            auto level_node = [&](const Level &L, int x, int32_t kind) {
                 HostNode h;
                 h.n = blank_node();
-                h.n.kind = x == F ? (emit ? kEmit : kCount) : kEnum;
+                h.n.kind = kind;
                 h.n.level = x;
                 h.n.isect = L.isect; h.n.diff = L.diff; h.n.lo = L.lo; h.n.hi = L.hi; h.n.excl = L.excl;
                 h.n.t_isect = L.t_isect; h.n.t_diff = L.t_diff; h.n.base = L.base;
                 h.n.label = L.label;
                 h.n.group = L.group;
                 h.avs = L.avs;
-                if (x == F) {
+                if (kind != kEnum) {
                     h.n.plan = (int32_t)pi;
-                    h.n.mult = p.mult;
-                    h.n.k = plans[pi]->k;
-                    for (int y = 0; y <= F; y++) h.n.pv[y] = (int8_t)p.lev[y].pv;
-                    for (int y = 0; y < F; y++)
-                        if (plans[pi]->anchor >= 0 && p.lev[y].pv == plans[pi]->anchor) h.n.anchor_level = y;
+                    h.n.anchor_level = anchor_level;
                 }
+                return h;
+            };
+            for (int x = H[cur].n.level + 1; x < F; x++) {
+                HostNode h = level_node(p.lev[x], x, kEnum);
                 h.key = node_key(h.n, h.avs);
                 cur = child(cur, std::move(h));
+            }
+            // a product: its factor nodes, then the count node that closes
+            // it, as consecutive siblings of their own (keys never shared)
+            const std::string own = p.factors.empty() ? std::string() : "#" + std::to_string(n_programs);
+            for (const Level &L : p.factors) {
+                HostNode h = level_node(L, F, kFactor);
+                h.key = node_key(h.n, h.avs) + own;
+                child(cur, std::move(h));
+            }
+            if (F > H[cur].n.level) {
+                HostNode h = level_node(p.lev[F], F, emit ? kEmit : kCount);
+                h.n.mult = p.mult;
+                h.n.k = plans[pi]->k;
+                for (int y = 0; y <= F; y++) h.n.pv[y] = (int8_t)p.lev[y].pv;
+                h.key = node_key(h.n, h.avs) + own;
+                child(cur, std::move(h));
             }
         }
     }

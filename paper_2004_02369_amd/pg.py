@@ -255,8 +255,7 @@ class Plan:
         for _ in range(next(it)):
             nl = next(it)
             lo, hi = next(it) & 0xFFFFFFFF, next(it) & 0xFFFFFFFF
-            levels = []
-            for _ in range(nl):
+            def level():
                 keys = ["isect", "diff", "lo", "hi", "excl", "t_isect", "t_diff"]
                 L = {k: next(it) & 0xFFFFFFFF for k in keys}
                 L.update(base=next(it), label=next(it), group=next(it), pv=next(it))
@@ -265,8 +264,10 @@ class Plan:
                     nbr, lab = next(it) & 0xFFFFFFFF, next(it)
                     avs.append({"nbr": nbr, "label": lab, "xmask": [next(it) & 0xFFFFFFFF for _ in range(16)]})
                 L["avs"] = avs
-                levels.append(L)
-            progs.append({"mult": lo | hi << 32, "levels": levels})
+                return L
+            levels = [level() for _ in range(nl)]
+            factors = [level() for _ in range(next(it))]
+            progs.append({"mult": lo | hi << 32, "levels": levels, "factors": factors})
         return progs
 
     def free(self):

@@ -5,7 +5,9 @@ plan compiler's output (symmetry breaking, core, matching orders, groups,
 anti-vertex triggers, base sets) against the oracle on the CPU, with no
 GPU involved.  It also asserts the invariants the GPU relies on: every
 candidate differs from every earlier image, a level's base set contains
-its candidates, and t_isect / t_diff are what the base leaves untested."""
+its candidates, t_isect / t_diff are what the base leaves untested, and a
+program's factor sets never share a vertex with each other or with the
+last level's candidates (which makes their product exact)."""
 from __future__ import annotations
 
 import math
@@ -60,9 +62,10 @@ def _ok(v, L, m, adj, labels):
     return True
 
 
-def _walk(n, adj, labels, levels, emit_fn=None):
+def _walk(n, adj, labels, levels, emit_fn=None, factors=()):
     F = len(levels) - 1
-    for x, L in enumerate(levels):
+    assert emit_fn is None or not factors
+    for x, L in list(enumerate(levels)) + [(F, Fl) for Fl in factors]:
         if L["base"] >= 0:
             B = levels[L["base"]]
             assert L["isect"] == L["t_isect"] | B["isect"] and L["diff"] == L["t_diff"] | B["diff"]
@@ -84,7 +87,20 @@ def _walk(n, adj, labels, levels, emit_fn=None):
                 for v in cands:
                     emit_fn(m + [v])
                 return len(cands)
-            return math.comb(len(cands), L["group"])
+            ways = math.comb(len(cands), L["group"])
+            # factors: independent groups at this depth; the product is
+            # exact only if no two of these sets can share a vertex
+            seen = set(cands)
+            for Fl in factors:
+                fc = [v for v in range(n) if _ok(v, Fl, m, adj, labels)]
+                for v in fc:
+                    assert v not in m, "factor candidate equals an earlier image"
+                if Fl["base"] >= 0:
+                    assert set(fc) <= set(sets[Fl["base"]]), "base set does not contain the candidates"
+                assert not (seen & set(fc)), "factor sets overlap"
+                seen |= set(fc)
+                ways *= math.comb(len(fc), Fl["group"])
+            return ways
         return sum(rec(x + 1, m + [v], sets + [cands]) for v in cands)
 
     return rec(0, [], [])
@@ -93,7 +109,7 @@ def _walk(n, adj, labels, levels, emit_fn=None):
 def interp_count(graph, programs, labels=None) -> int:
     n, src, dst = graph
     adj = _adj(n, src, dst)
-    return sum(p["mult"] * _walk(n, adj, labels, p["levels"]) for p in programs)
+    return sum(p["mult"] * _walk(n, adj, labels, p["levels"], factors=p.get("factors", ())) for p in programs)
 
 
 def interp_enumerate(graph, programs, k, labels=None) -> list[tuple]:
@@ -101,7 +117,7 @@ def interp_enumerate(graph, programs, k, labels=None) -> list[tuple]:
     adj = _adj(n, src, dst)
     out = []
     for p in programs:
-        assert p["mult"] == 1
+        assert p["mult"] == 1 and not p.get("factors")
         pv = [L["pv"] for L in p["levels"]]
 
         def emit(m, pv=pv):

@@ -134,3 +134,46 @@ def test_domains_at_labelled_workload_size(pg, orc):
     want = {i: orc.domains(og, s) for i, s in enumerate(specs)}
     for (i, u), g_ in zip(jobs, got):
         assert g_ == want[i][u], (specs[i], u)
+
+
+def _random_labelled(rng, k):
+    edges = {(int(rng.integers(0, v)), v) for v in range(1, k)}
+    for a in range(k):
+        for b in range(a + 1, k):
+            if rng.random() < 0.2:
+                edges.add((a, b))
+    # mostly distinct labels (so independent groups occur), a few unlabelled
+    labels = [int(x) if rng.random() > 0.1 else -1 for x in rng.integers(0, 4, k)]
+    spec = {"k": k, "edges": sorted(edges), "labels": labels}
+    if rng.random() < 0.25:
+        spec["induced"] = True
+    return spec
+
+
+@pytest.mark.parametrize("knobs", [{}, {"flags": 4, "chunk": 1}, {"batch_max_avg": 4, "hub_min_degree": -1}])
+def test_products_of_independent_groups(pg, orc, case, knobs):
+    """Random labelled patterns whose count programs multiply independent
+    groups (factor nodes), batched with plans that have none: counts,
+    existence and domains against the oracle, over launch shapes that reach
+    the root, set and flattened batches."""
+    g, lab, _ = case
+    og = orc.Graph.from_tuple(g, lab)
+    G = pg.load_graph(*g, labels=lab, device=0)
+    rng = np.random.Generator(np.random.PCG64(123))
+    specs = [_random_labelled(rng, int(rng.integers(3, 6))) for _ in range(32)]
+    plans = [pg.plan_pattern(s) for s in specs]
+    n_fac = sum(bool(p["factors"]) for pl in plans for p in pl.programs())
+    say(f"{len(specs)} random labelled patterns ({n_fac} count programs with factors), knobs {knobs}")
+    assert n_fac >= 15
+    want = [orc.count(og, s) for s in specs]
+    assert pg.count(G, plans, **knobs) == want
+    for s, p, w in zip(specs[:8], plans[:8], want[:8]):
+        assert pg.exists(G, p) == (w > 0), s
+    jobs = [(i, u) for i in range(0, len(specs), 3) for u in range(specs[i]["k"])]
+    aplans = [pg.plan_pattern(specs[i], anchor=u) for i, u in jobs]
+    dom = {i: orc.domains(og, specs[i]) for i in range(0, len(specs), 3)}
+    sizes = []
+    for s in range(0, len(aplans), 64):
+        sizes += pg.domain_sizes(G, aplans[s:s + 64], **knobs)
+    for (i, u), sz in zip(jobs, sizes):
+        assert sz == dom[i][u], (specs[i], u)

@@ -205,6 +205,73 @@ def test_labelled_programs(orc):
             assert interp_count(g, pg.plan_pattern(spec).programs(), labels=lab) == orc.count(og, spec)
 
 
+def _random_labelled_pattern(rng, k):
+    """A connected k-vertex pattern (random spanning tree plus extra edges),
+    labels drawn from {-1, 0, 1, 2} so that both repeated and distinct
+    labels occur; vertex-induced one time in four."""
+    edges = {(int(rng.integers(0, v)), v) for v in range(1, k)}
+    for a, b in itertools.combinations(range(k), 2):
+        if rng.random() < 0.2:
+            edges.add((a, b))
+    spec = {"k": k, "edges": sorted(edges), "labels": [int(x) for x in rng.integers(-1, 3, k)]}
+    if rng.random() < 0.25:
+        spec["induced"] = True
+    return spec
+
+
+FACTOR_SHAPES = [
+    # (spec, anchor, factor group sizes of every count program)
+    ({"k": 4, "edges": [(0, 1), (0, 2), (0, 3)], "labels": [1, 0, 2, 3]}, None, [1, 1]),
+    ({"k": 4, "edges": [(0, 1), (0, 2), (0, 3)], "labels": [1, 0, 0, 1]}, None, [1]),
+    ({"k": 5, "edges": [(0, 1), (0, 2), (0, 3), (0, 4)], "labels": [0, 1, 1, 2, 3]}, 1, [1, 1]),
+    ({"k": 4, "edges": [(0, 1), (1, 2), (2, 3)], "labels": [0, 1, 2, 3]}, None, [1]),
+    ({"k": 4, "edges": [(0, 1), (1, 2), (2, 3)], "labels": [0, 1, 2, 3]}, 1, [1]),
+    # the two ends may be one vertex (same label, or one unlabelled): enumerated
+    ({"k": 4, "edges": [(0, 1), (1, 2), (2, 3)], "labels": [0, 1, 1, 0]}, None, []),
+    ({"k": 4, "edges": [(0, 1), (1, 2), (2, 3)], "labels": [-1, 1, 2, 3]}, None, []),
+    ({"k": 4, "edges": [(0, 1), (0, 2), (0, 3)]}, None, []),
+]
+
+
+@pytest.mark.parametrize("fi", range(len(FACTOR_SHAPES)))
+def test_factor_groups_chosen(fi):
+    """Independent groups (a label no other non-core vertex can carry)
+    become factors of the count programs; enumeration never uses them."""
+    spec, anchor, want = FACTOR_SHAPES[fi]
+    plan = pg.plan_pattern(spec, anchor=anchor)
+    for prog in plan.programs():
+        assert sorted(f["group"] for f in prog["factors"]) == want, prog
+        F = len(prog["levels"]) - 1
+        for f in prog["factors"]:
+            assert f["label"] >= 0 and not f["avs"]
+            assert f["isect"] < (1 << F) and f["excl"] < (1 << F)
+    assert all(not p["factors"] for p in plan.programs(enum_mode=True))
+
+
+def test_factor_programs_count_like_oracle(orc):
+    """Random labelled patterns, plain and anchored: the count programs
+    (with their products of independent groups) give the oracle's count
+    and valid maps / |stabiliser of the anchor|; the interpreter also
+    asserts that no two sets of a product share a vertex."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    n_fac = 0
+    for trial in range(60):
+        k = int(rng.integers(3, 6))
+        spec = _random_labelled_pattern(rng, k)
+        g = gg.gnp(10, 0.5, seed=900 + trial)
+        lab = rng.integers(0, 3, 10).astype(np.int16)
+        og = orc.Graph.from_tuple(g, lab)
+        plan = pg.plan_pattern(spec)
+        n_fac += sum(len(p["factors"]) for p in plan.programs())
+        assert interp_count(g, plan.programs(), labels=lab) == orc.count(og, spec), (trial, spec)
+        valid = orc.valid_maps(og, spec)
+        for u in range(k):
+            ap = pg.plan_pattern(spec, anchor=u)
+            n_fac += sum(len(p["factors"]) for p in ap.programs())
+            assert interp_count(g, ap.programs(), labels=lab) == valid // ap.info()["aut"], (trial, spec, u)
+    assert n_fac > 20
+
+
 def test_partial_order_gives_one_map_per_orbit(orc):
     """Grochow-Kellis: among the valid maps, exactly count() satisfy the
     partial order (the PRG-U relation read backwards)."""
