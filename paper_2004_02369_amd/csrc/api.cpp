@@ -47,6 +47,7 @@ struct LaunchPlan {
     std::vector<char> image;  // nodes | anti-vertex checks | roots
     size_t a_off = 0, r_off = 0;
     bool with_av = false;
+    int variant = pg::kVarPlain;
     int grid = 0, chunk = 0;
     long long n_et = 0, n_vt = 0;
     int enum_levels = 0;
@@ -81,7 +82,7 @@ struct pg_graph {
     int32_t device = 0;
     int32_t n_cu = 0;
     int64_t wall_khz = 0;  // device wall-clock ticks per millisecond
-    int32_t blocks_per_cu[2] = {0, 0};  // resident match_kernel wavefronts per CU (without / with anti-vertices)
+    int32_t blocks_per_cu[3] = {0, 0, 0};  // resident wavefronts per CU of each kernel variant (pg::Variant)
     bool labelled = false;
     std::vector<int32_t> perm;  // rank -> original id
     // device arrays
@@ -344,8 +345,7 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         PG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
         if (khz <= 0) { set_error("device reports no wall-clock rate"); return PG_EDEVICE; }
         g->wall_khz = khz;
-        g->blocks_per_cu[0] = pg::match_blocks_per_cu(false);
-        g->blocks_per_cu[1] = pg::match_blocks_per_cu(true);
+        for (int v = 0; v < 3; v++) g->blocks_per_cu[v] = pg::match_blocks_per_cu(v);
         pg_status st;
         if ((st = upload(&g->rp, rp, &g->device_bytes))) return st;
         if ((st = upload(&g->col, col, &g->device_bytes))) return st;
@@ -397,8 +397,8 @@ pg_status pg_graph_info(const pg_graph *g, pg_graph_info_t *out) {
     out->labelled = g->labelled ? 1 : 0;
     out->device = g->device;
     out->perm = g->perm.data();
-    out->resident_waves[0] = g->n_cu * g->blocks_per_cu[0];
-    out->resident_waves[1] = g->n_cu * g->blocks_per_cu[1];
+    out->resident_waves[0] = g->n_cu * g->blocks_per_cu[pg::kVarPlain];
+    out->resident_waves[1] = g->n_cu * g->blocks_per_cu[pg::kVarAV];
     out->hub_count = g->n - g->hub_start;
     out->hub_min_degree = g->hub_start < g->n ? (int32_t)g->hub_min_deg : 0;
     return PG_OK;
@@ -517,12 +517,19 @@ pg_status check_args(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, 
     return PG_OK;
 }
 
-// shape of a launch for a built trie
-void shape(const pg_graph *g, const pg_run_config *cfg, LaunchPlan &L) {
+// shape of a launch for a built trie (marks: domain bitmaps are on)
+void shape(const pg_graph *g, const pg_run_config *cfg, LaunchPlan &L, bool marks) {
     const pg::Trie &T = L.trie;
     L.with_av = !T.avs.empty();
-    // persistent grid: exactly the wavefronts that can be resident at once
-    L.grid = cfg && cfg->grid_waves ? cfg->grid_waves : g->n_cu * g->blocks_per_cu[L.with_av ? 1 : 0];
+    bool pre = marks;
+    for (int32_t r : T.roots)
+        if (T.nodes[r].label0 >= 0 || T.nodes[r].label1 >= 0) pre = true;
+    for (const pg::Node &n : T.nodes)
+        if (n.kind == pg::kFactor) pre = true;
+    L.variant = L.with_av ? pg::kVarAV : pre ? pg::kVarPre : pg::kVarPlain;
+    // persistent grid: exactly the wavefronts of this variant that can be
+    // resident at once
+    L.grid = cfg && cfg->grid_waves ? cfg->grid_waves : g->n_cu * g->blocks_per_cu[L.variant];
     L.n_et = T.has_edge_root ? (long long)g->m : 0;
     L.n_vt = T.has_vertex_root ? (long long)g->n : 0;
     L.chunk = cfg && cfg->chunk ? cfg->chunk : 64;
@@ -601,12 +608,6 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.mark_words = la.mark_words;
     P.task_begin = la.task_begin;
     P.task_end = la.task_end;
-    P.root_labels = 0;
-    for (int32_t r : L.trie.roots)
-        if (L.trie.nodes[r].label0 >= 0 || L.trie.nodes[r].label1 >= 0) P.root_labels = 1;
-    P.factors = 0;
-    for (const pg::Node &n : L.trie.nodes)
-        if (n.kind == pg::kFactor) P.factors = 1;
     return P;
 }
 
@@ -647,13 +648,13 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
             g->trie_valid = false;
             return st;
         }
-        shape(g, cfg, g->launch);
+        shape(g, cfg, g->launch, la.sizes != nullptr);
         g->trie_key = key;
         g->trie_emit = emit;
         g->trie_valid = true;
     }
     LaunchPlan &L = g->launch;
-    shape(g, cfg, L);  // the knobs may differ between calls
+    shape(g, cfg, L, la.sizes != nullptr);  // the knobs may differ between calls
     if (la.task_begin < 0 || la.task_end < 0 || (la.task_end > 0 && la.task_end <= la.task_begin) ||
         la.task_end > L.n_et + L.n_vt || (la.task_end == 0 && la.task_begin > 0)) {
         set_error("bad root-task window");
@@ -708,7 +709,7 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     PG_HIP(hipEventCreate(&e0));
     PG_HIP(hipEventCreate(&e1));
     PG_HIP(hipEventRecord(e0, s));
-    hipError_t le = pg::launch_match(P, L.grid, L.with_av, s);
+    hipError_t le = pg::launch_match(P, L.grid, L.variant, s);
     if (le != hipSuccess) {
         edestroy(e0);
         edestroy(e1);
@@ -964,7 +965,7 @@ static pg_status prepare_job(pg_graph *g, const pg_plan *const *plans, int32_t n
     std::memset(&c, 0, sizeof(c));
     if (cfg) c = *cfg;
     if (mode == PG_JOB_EXISTS && !c.chunk) c.chunk = 1;  // poll the stop flag often
-    shape(g, &c, *L);
+    shape(g, &c, *L, false);
     return PG_OK;
 }
 
@@ -1037,7 +1038,7 @@ pg_status pg_submit(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, i
         PG_HIP(hipEventCreate(&j->ek));
         PG_HIP(hipEventCreate(&j->e1));
         PG_HIP(hipEventRecord(j->e0, j->s));
-        hipError_t le = pg::launch_match(P, j->L.grid, j->L.with_av, j->s);
+        hipError_t le = pg::launch_match(P, j->L.grid, j->L.variant, j->s);
         if (le != hipSuccess) {
             set_error(std::string("kernel launch: ") + hipGetErrorString(le));
             return PG_EDEVICE;

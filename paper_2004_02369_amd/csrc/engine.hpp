@@ -50,18 +50,19 @@ struct KParams {
     long long mark_words;
     long long task_begin;      // root tasks [task_begin, task_end) of this launch; task_end 0 = to the last
     long long task_end;
-    int32_t root_labels;       // some root node has a label (roots are then filtered before loading rows)
-    int32_t factors;           // the trie holds kFactor nodes (selects a variant that evaluates them)
 };
 
-// with_av: the trie holds anti-vertex checks (selects the kernel variant)
-hipError_t launch_match(const KParams &P, int grid, bool with_av, hipStream_t s);
+// Kernel variants: plain; "pre" for labelled roots, domain marks or factor
+// nodes (roots are filtered before their rows load); anti-vertex checks.
+enum Variant : int { kVarPlain = 0, kVarPre = 1, kVarAV = 2 };
+
+hipError_t launch_match(const KParams &P, int grid, int variant, hipStream_t s);
 
 // out[r] += number of set bits in row r of `rows` bitmaps of `words` words each
 hipError_t launch_popcount(const uint32_t *bits, long long words, int rows, unsigned long long *out,
                            hipStream_t s);
 
-// resident wavefronts (one per workgroup) per compute unit for match_kernel
-int match_blocks_per_cu(bool with_av);
+// resident wavefronts (one per workgroup) per compute unit of a variant
+int match_blocks_per_cu(int variant);
 
 }  // namespace pg
