@@ -1372,8 +1372,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) ma
 }
 
 // labelled roots or domain marks: roots are filtered before their rows load;
-// also the variant that evaluates factor nodes
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) match_kernel_pre(KParams P) {
+// also the variant that evaluates factor nodes.  Held to 128 VGPRs (four
+// waves per SIMD): its launches, e.g. 64 anchored labelled plans of a
+// mining round, are short, and there five waves measured slower
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) match_kernel_pre(KParams P) {
     match_body<false, true>(P);
 }
 
