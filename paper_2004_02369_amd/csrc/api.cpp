@@ -82,7 +82,7 @@ struct pg_graph {
     int32_t device = 0;
     int32_t n_cu = 0;
     int64_t wall_khz = 0;  // device wall-clock ticks per millisecond
-    int32_t blocks_per_cu[3] = {0, 0, 0};  // resident wavefronts per CU of each kernel variant (pg::Variant)
+    int32_t blocks_per_cu[pg::kNumVariants] = {};  // resident wavefronts per CU of each kernel variant (pg::Variant)
     bool labelled = false;
     std::vector<int32_t> perm;  // rank -> original id
     // device arrays
@@ -345,7 +345,7 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         PG_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
         if (khz <= 0) { set_error("device reports no wall-clock rate"); return PG_EDEVICE; }
         g->wall_khz = khz;
-        for (int v = 0; v < 3; v++) g->blocks_per_cu[v] = pg::match_blocks_per_cu(v);
+        for (int v = 0; v < pg::kNumVariants; v++) g->blocks_per_cu[v] = pg::match_blocks_per_cu(v);
         pg_status st;
         if ((st = upload(&g->rp, rp, &g->device_bytes))) return st;
         if ((st = upload(&g->col, col, &g->device_bytes))) return st;
@@ -517,21 +517,31 @@ pg_status check_args(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, 
     return PG_OK;
 }
 
-// shape of a launch for a built trie (marks: domain bitmaps are on)
-void shape(const pg_graph *g, const pg_run_config *cfg, LaunchPlan &L, bool marks) {
+// root tasks from which a count launch with enumeration levels takes the
+// five-wave kernel variant
+constexpr long long kLongLaunchTasks = 1ll << 18;
+
+// shape of a launch for a built trie (mode: pg::RunMode; marks: domain
+// bitmaps are on)
+void shape(const pg_graph *g, const pg_run_config *cfg, LaunchPlan &L, int mode, bool marks) {
     const pg::Trie &T = L.trie;
     L.with_av = !T.avs.empty();
-    bool pre = marks;
+    L.n_et = T.has_edge_root ? (long long)g->m : 0;
+    L.n_vt = T.has_vertex_root ? (long long)g->n : 0;
+    bool pre = marks, enums = false;
     for (int32_t r : T.roots)
         if (T.nodes[r].label0 >= 0 || T.nodes[r].label1 >= 0) pre = true;
-    for (const pg::Node &n : T.nodes)
+    for (const pg::Node &n : T.nodes) {
         if (n.kind == pg::kFactor) pre = true;
-    L.variant = L.with_av ? pg::kVarAV : pre ? pg::kVarPre : pg::kVarPlain;
+        if (n.kind == pg::kEnum) enums = true;
+    }
+    // five waves per SIMD pay off on long counts that enumerate; shorter
+    // launches measured faster at four (no spills)
+    const bool long_count = mode == pg::kModeCount && enums && L.n_et + L.n_vt >= kLongLaunchTasks;
+    L.variant = L.with_av ? pg::kVarAV : pre ? pg::kVarPre : long_count ? pg::kVarPlain : pg::kVarLight;
     // persistent grid: exactly the wavefronts of this variant that can be
     // resident at once
     L.grid = cfg && cfg->grid_waves ? cfg->grid_waves : g->n_cu * g->blocks_per_cu[L.variant];
-    L.n_et = T.has_edge_root ? (long long)g->m : 0;
-    L.n_vt = T.has_vertex_root ? (long long)g->n : 0;
     L.chunk = cfg && cfg->chunk ? cfg->chunk : 64;
     // scratch: one set per enumeration level (levels 2 .. max_level-2) plus
     // the arena of batched expansions
@@ -648,13 +658,13 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
             g->trie_valid = false;
             return st;
         }
-        shape(g, cfg, g->launch, la.sizes != nullptr);
+        shape(g, cfg, g->launch, la.mode, la.sizes != nullptr);
         g->trie_key = key;
         g->trie_emit = emit;
         g->trie_valid = true;
     }
     LaunchPlan &L = g->launch;
-    shape(g, cfg, L, la.sizes != nullptr);  // the knobs may differ between calls
+    shape(g, cfg, L, la.mode, la.sizes != nullptr);  // the knobs may differ between calls
     if (la.task_begin < 0 || la.task_end < 0 || (la.task_end > 0 && la.task_end <= la.task_begin) ||
         la.task_end > L.n_et + L.n_vt || (la.task_end == 0 && la.task_begin > 0)) {
         set_error("bad root-task window");
@@ -965,7 +975,7 @@ static pg_status prepare_job(pg_graph *g, const pg_plan *const *plans, int32_t n
     std::memset(&c, 0, sizeof(c));
     if (cfg) c = *cfg;
     if (mode == PG_JOB_EXISTS && !c.chunk) c.chunk = 1;  // poll the stop flag often
-    shape(g, &c, *L, false);
+    shape(g, &c, *L, mode == PG_JOB_EXISTS ? pg::kModeExists : pg::kModeCount, false);
     return PG_OK;
 }
 

@@ -58,23 +58,23 @@ struct Lds {
     int32_t tro0[kP], tro1[kP];
     int32_t trl0[kP], trl1[kP], tru0[kP], tru1[kP];
     // level-2 candidates of a whole task batch, in the arena: task t owns
-    // [tstart[t], tstart[t + 1]); prefixes of a task batch record their task
+    // [tstart[t], tstart[t] + tcnt[t]); prefixes of a task batch record their task
     int32_t tstart[kP + 1];
+    int32_t tcnt[kP];
     int32_t ptask[kP];            // parent slot of each prefix
     // prefix batch: value and row of the varying level
     int32_t pv0[kP];
     int32_t po0[kP];
     int32_t pl0[kP];
     int32_t pu0[kP];
+    int32_t pidx[kP];             // index of the prefix in its own set (set batches)
     int32_t boff[kP];             // direct: the base range; complement: the single positive operand (enc)
     int32_t blen[kP];
     int32_t p1own[kP];            // complement: owner of that operand's row, -1 for a set
     int8_t pmode[kP];             // -1 skip, 0 direct, 1 complement
     int8_t pdrv[kP];
-    // per prefix: direct mode counts passing candidates up from 0;
-    // complement mode counts down from |P1| minus the excluded images
-    // (also the per-parent survivor counter of a flattened expansion)
     uint32_t pcnt[kP];
+    int32_t pconst[kP];
     int32_t seg_start[kSeg + 1];
     uint8_t seg_prefix[kSeg];
     int32_t seg_off[kSeg];        // segment start (enc)
@@ -198,14 +198,13 @@ struct Ctx {
     int plev0;      // levels taken from each prefix's parent slot (-1 none):
     int plev1;      //   root tasks give levels 0 and 1, set parents one level
     int amode;      // 1: the vl0 level's set is the arena slice of the prefix's parent
-    int pbase;      // index of prefix 0's vl0 element in the batch's set (arena when amode)
     int anc_level;  // domains: the current root's anchor level (0 / 1, -1 none) and plan
     int anc_plan;
     int32_t *arena; // this wave's arena for batched expansions
     unsigned long long acc;  // lane p: running count of plan p
 
     __device__ Ctx(const KParams &p, Lds &l, int32_t *b, int ln)
-        : P(p), L(l), buf0(b), lane(ln), vl0(-1), plev0(-1), plev1(-1), amode(0), pbase(0), anc_level(-1), anc_plan(0),
+        : P(p), L(l), buf0(b), lane(ln), vl0(-1), plev0(-1), plev1(-1), amode(0), anc_level(-1), anc_plan(0),
           arena(nullptr), acc(0) {}
 
     __device__ __forceinline__ int32_t *setbuf(int level) const { return buf0 + (long long)(level - 2) * P.set_cap; }
@@ -261,18 +260,10 @@ struct Ctx {
         const int32_t *B;
         int32_t Bn, cur, ci;
         if (l >= 0 && bl == vl0) {
-            if (amode) {
-                const int t = L.ptask[l];
-                const int32_t t0 = L.tstart[t];
-                B = arena + t0;
-                Bn = L.tstart[t + 1] - t0;
-                ci = pbase + l - t0;
-            } else {
-                B = setbuf(bl);
-                Bn = L.set_len[bl];
-                ci = pbase + l;
-            }
+            B = amode ? arena + L.tstart[L.ptask[l]] : setbuf(bl);
+            Bn = amode ? L.tcnt[L.ptask[l]] : L.set_len[bl];
             cur = L.pv0[l];
+            ci = L.pidx[l];
         } else if (l >= 0 && bl == plev0) {
             B = setbuf(bl);
             Bn = L.set_len[bl];
@@ -387,9 +378,8 @@ struct Ctx {
 
     // ---------------------------------------------------------------
     // Flattened evaluation of count / emit node N (level x) over np
-    // prefixes already loaded into the batch arrays (pv0/po0/pl0/pu0 for
-    // the varying level vl0, with pbase; ptask for parent-slot levels;
-    // pmode).
+    // prefixes already loaded into the batch arrays (pv0/po0/pl0/pu0 and
+    // pidx for the varying level vl0, ptask for parent-slot levels, pmode).
     __device__ __forceinline__ void count_batch(const Node &N, int np) {
         const int x = N.level;
         const bool emit = N.kind == kEmit;
@@ -501,6 +491,7 @@ struct Ctx {
                 }
                 atomicAdd(&L.bytes, 4ull * (unsigned long long)bytes);
             }
+            L.pcnt[l] = 0;
             L.pdrv[l] = (int8_t)drv;
             L.p1own[l] = downer;
             if (complement) {
@@ -511,7 +502,7 @@ struct Ctx {
             }
             if (!complement) {
                 L.pmode[l] = 0;
-                L.pcnt[l] = 0;
+                L.pconst[l] = 0;
                 sp0 = dptr;
                 sl0 = dlen;
                 so0 = downer;
@@ -529,7 +520,7 @@ struct Ctx {
                     for (uint32_t t = N.t_diff; t && !in_d; t &= t - 1) in_d = in_row(P, row(__builtin_ctz(t), l), v);
                     if (!in_d) c--;
                 }
-                L.pcnt[l] = (uint32_t)c;
+                L.pconst[l] = c;
                 // pack the non-empty difference segments, keeping their order
                 int k = 0;
                 const int32_t *q0 = nullptr, *q1 = nullptr, *q2 = nullptr;
@@ -632,7 +623,6 @@ struct Ctx {
             const int32_t t = tb + lane;
             bool ok = false;
             int l = 0;
-            uint32_t inc = 1u;  // direct: +1 per passing candidate; complement: -1
             const int32_t e = e_next;
             const int s_cur = s;
             if (t + 64 < total) {
@@ -647,7 +637,6 @@ struct Ctx {
                 } else {
                     // complement term: e in D_k counts if e in P1 and in no
                     // earlier D of this prefix (the segments just before)
-                    inc = 0xFFFFFFFFu;
                     ok = in_range(P, dec(L.boff[l]), L.blen[l], L.p1own[l], e);
                     for (int s2 = s - 1; ok && s2 >= 0 && L.seg_prefix[s2] == l; s2--)
                         ok = !in_range(P, dec(L.seg_off[s2]), L.seg_start[s2 + 1] - L.seg_start[s2], L.seg_own[s2], e);
@@ -667,7 +656,7 @@ struct Ctx {
                     }
                 }
             } else if (ok) {
-                atomicAdd(&L.pcnt[l], inc);
+                atomicAdd(&L.pcnt[l], 1u);
             }
         }
         wsync();
@@ -678,7 +667,9 @@ struct Ctx {
             // count node after it closes the product
             const bool factor = kFac && N.kind == kFactor;
             if (lane < np && L.pmode[lane] >= 0) {
-                const unsigned long long c = (unsigned long long)L.pcnt[lane];
+                const unsigned long long c = L.pmode[lane] == 0
+                                                 ? (unsigned long long)L.pcnt[lane]
+                                                 : (unsigned long long)(L.pconst[lane] - (int32_t)L.pcnt[lane]);
                 contrib = choose(c, N.group, &ovf);
                 if constexpr (kFac) {
                     unsigned long long q;
@@ -750,8 +741,8 @@ struct Ctx {
                 L.po0[lane] = (int32_t)o;
                 L.pl0[lane] = (int32_t)(P.rp[v + 1] - o);
                 L.pu0[lane] = P.up[v];
+                L.pidx[lane] = s + lane;
             }
-            pbase = s;
             for (int c = 0; c < first_enum; c++) {
                 if (lane < np) L.pmode[lane] = 0;
                 wsync();
@@ -901,7 +892,7 @@ struct Ctx {
                 L.seg_prefix[sidx] = (uint8_t)lane;
                 L.seg_off[sidx] = enc(dptr);
             }
-            L.pcnt[lane] = 0;  // survivors per parent
+            L.tcnt[lane] = 0;
             if (lane == 0) L.seg_start[nseg] = total;
             wsync();
             int32_t out_n = 0;
@@ -940,14 +931,14 @@ struct Ctx {
                 const unsigned long long bal = __ballot(pass);
                 if (pass) {
                     arena[out_n + (int32_t)__popcll(bal & ((1ull << lane) - 1ull))] = e;
-                    atomicAdd(&L.pcnt[l], 1u);
+                    atomicAdd(&L.tcnt[l], 1);
                 }
                 out_n += (int32_t)__popcll(bal);
             }
             wsync();
             // survivors are in parent order: slices start at the scan of the counts
             int ntot = 0;
-            const int32_t tc = lane < np ? (int32_t)L.pcnt[lane] : 0;
+            const int32_t tc = lane < np ? L.tcnt[lane] : 0;
             const int32_t st = wave_scan_excl(tc, lane, &ntot);
             if (lane < np) L.tstart[lane] = st;
             if (lane == 0) L.tstart[np] = ntot;
@@ -973,12 +964,12 @@ struct Ctx {
                     const int32_t v = arena[idx];
                     const long long o = P.rp[v];
                     L.ptask[lane] = t_lo;
+                    L.pidx[lane] = idx - L.tstart[t_lo];
                     L.pv0[lane] = v;
                     L.po0[lane] = (int32_t)o;
                     L.pl0[lane] = (int32_t)(P.rp[v + 1] - o);
                     L.pu0[lane] = P.up[v];
                 }
-                pbase = s0;
                 for (int c = 0; c < cc; c++) {
                     if (lane < np2) L.pmode[lane] = 0;
                     wsync();
@@ -1364,10 +1355,18 @@ __device__ __forceinline__ void match_body(const KParams P) {
     if (lane == 0 && L.bytes) atomicAdd(P.bytes_ctr, L.bytes);
 }
 
-// the common variant is held to 96 VGPRs and 8 KB of LDS: five wavefronts
-// per SIMD (the kernel is bound by load latency, so resident waves are what
-// hides it; most of the few spills this costs sit in the task-claim loop)
+// Long count launches: held to 96 VGPRs (five wavefronts per SIMD by
+// registers; 8.9 KB of LDS per wave then allows 18 per CU).  The kernel is
+// bound by load latency, so resident waves are what hides it; most of the
+// few spills this costs sit in the task-claim loop.
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) match_kernel(KParams P) {
+    match_body<false, false>(P);
+}
+
+// The same program at 128 VGPRs and four wavefronts per SIMD, without
+// spills, for launches that end quickly (existence, emission, tries without
+// enumeration levels, small task sets), where it measured faster
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) match_kernel_light(KParams P) {
     match_body<false, false>(P);
 }
 
@@ -1382,9 +1381,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ma
 __global__ void __launch_bounds__(64) match_kernel_av(KParams P) { match_body<true, true>(P); }
 
 static const void *variant_fn(int variant) {
-    return variant == kVarAV ? reinterpret_cast<const void *>(match_kernel_av)
-           : variant == kVarPre ? reinterpret_cast<const void *>(match_kernel_pre)
-                                : reinterpret_cast<const void *>(match_kernel);
+    switch (variant) {
+    case kVarAV: return reinterpret_cast<const void *>(match_kernel_av);
+    case kVarPre: return reinterpret_cast<const void *>(match_kernel_pre);
+    case kVarLight: return reinterpret_cast<const void *>(match_kernel_light);
+    default: return reinterpret_cast<const void *>(match_kernel);
+    }
 }
 
 int match_blocks_per_cu(int variant) {
@@ -1417,6 +1419,7 @@ hipError_t launch_popcount(const uint32_t *bits, long long words, int rows, unsi
 hipError_t launch_match(const KParams &P, int grid, int variant, hipStream_t s) {
     if (variant == kVarAV) hipLaunchKernelGGL(match_kernel_av, dim3(grid), dim3(64), 0, s, P);
     else if (variant == kVarPre) hipLaunchKernelGGL(match_kernel_pre, dim3(grid), dim3(64), 0, s, P);
+    else if (variant == kVarLight) hipLaunchKernelGGL(match_kernel_light, dim3(grid), dim3(64), 0, s, P);
     else hipLaunchKernelGGL(match_kernel, dim3(grid), dim3(64), 0, s, P);
     return hipGetLastError();
 }

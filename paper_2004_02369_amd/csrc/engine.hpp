@@ -52,9 +52,12 @@ struct KParams {
     long long task_end;
 };
 
-// Kernel variants: plain; "pre" for labelled roots, domain marks or factor
-// nodes (roots are filtered before their rows load); anti-vertex checks.
-enum Variant : int { kVarPlain = 0, kVarPre = 1, kVarAV = 2 };
+// Kernel variants: plain (long count launches, five waves per SIMD);
+// "pre" for labelled roots, domain marks or factor nodes (roots are
+// filtered before their rows load); anti-vertex checks; light (the plain
+// program at four waves per SIMD, for launches that end quickly).
+enum Variant : int { kVarPlain = 0, kVarPre = 1, kVarAV = 2, kVarLight = 3 };
+constexpr int kNumVariants = 4;
 
 hipError_t launch_match(const KParams &P, int grid, int variant, hipStream_t s);
 
