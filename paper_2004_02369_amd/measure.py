@@ -5,6 +5,8 @@
                                                      # 21 induced 5-motifs + K5, batched vs one launch each
     python -m paper_2004_02369_amd.measure small     # launch-bound case: ER 2k/20k, batched vs singles
     python -m paper_2004_02369_amd.measure inversion # induced census via non-induced counts + inversion
+    python -m paper_2004_02369_amd.measure c3        # 21 induced 5-motifs + K5 on R-MAT scale 20 (16M edges):
+                                                     # each alone under a time limit, the finishing ones batched
 """
 from __future__ import annotations
 
@@ -84,6 +86,48 @@ def inversion(args, pg, gg, pt):
                           "inversion_s": best, "speedup": t_direct / best, "equal": inv == direct}), flush=True)
 
 
+def c3(args, pg, gg, pt):
+    """The 22-plan family (21 induced 5-motifs + K5) at full size: each plan
+    alone under a device time limit, then every plan that finished in one
+    launch (default and tuned knobs) against the sum of their single
+    launches.  Counts of a finished launch are exact; the batch must repeat
+    the singles' counts, and K5 must equal the induced K5 when both finish."""
+    from . import tune
+    t0 = time.perf_counter()
+    G = pg.load_graph(*gg.workload(args.workload), device=0)
+    _say(f"{args.workload}: n={G.n} m={G.m} d_max={G.d_max} ready in {time.perf_counter() - t0:.1f} s")
+    specs = pt.all_vertex_induced(5) + [pt.clique(5)]
+    plans = [pg.plan_pattern(s) for s in specs]
+    singles = []
+    for i, p in enumerate(plans):
+        try:
+            c, st = pg.count_ex(G, [p], time_limit_ms=args.limit_ms)
+            singles.append({"plan": i, "edges": specs[i]["edges"], "ms": st["kernel_ms"], "count": c[0]})
+        except pg.PGError as e:
+            if e.status != pg.PG_ETIMEDOUT:
+                raise
+            singles.append({"plan": i, "edges": specs[i]["edges"], "ms": None, "count": None})
+        _say(f"plan {i} {specs[i]['edges']}: {singles[-1]['ms']} ms, count {singles[-1]['count']}")
+    done = [r for r in singles if r["ms"] is not None]
+    batch = [plans[r["plan"]] for r in done]
+    out = {"measure": "c3", "workload": args.workload, "n": G.n, "m": G.m, "d_max": G.d_max,
+           "limit_ms": args.limit_ms, "singles": singles, "finished": len(done)}
+    if done:
+        c, st = pg.count_ex(G, batch)
+        assert c == [r["count"] for r in done], "batched counts differ from the single launches"
+        out["batched_ms"] = st["kernel_ms"]
+        out["singles_sum_ms"] = sum(r["ms"] for r in done)
+        out["batched_speedup"] = out["singles_sum_ms"] / st["kernel_ms"]
+        _say(f"batch of {len(done)}: {st['kernel_ms']:.1f} ms vs {out['singles_sum_ms']:.1f} ms one launch each")
+        tuned = tune.autotune(G, batch, budget_s=args.tune_budget, log=_say)
+        out["tuned"] = {"knobs": tuned["knobs"], "ms": tuned["ms"], "default_ms": tuned["default_ms"],
+                        "trials": len(tuned["trials"])}
+    if singles[-1]["count"] is not None and singles[-2]["count"] is not None:
+        assert singles[-1]["count"] == singles[-2]["count"], "K5 differs from the induced K5"
+        out["k5_equals_induced_k5"] = True
+    print(json.dumps(out), flush=True)
+
+
 def small(args, pg, gg, pt):
     """Launch-bound regime: the six induced 4-motifs on ER 2k/20k, one
     batched launch against six launches, best of several repetitions."""
@@ -107,9 +151,10 @@ def small(args, pg, gg, pt):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion"])
+    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion", "c3"])
     ap.add_argument("--workload", default=None)
     ap.add_argument("--limit-ms", type=int, default=600000)
+    ap.add_argument("--tune-budget", type=float, default=60.0)
     args = ap.parse_args(argv)
     import torch
     from . import graphgen as gg
@@ -124,6 +169,9 @@ def main(argv=None):
         motifs5(args, pg, gg, pt)
     elif args.what == "inversion":
         inversion(args, pg, gg, pt)
+    elif args.what == "c3":
+        args.workload = args.workload or "rmat20_16m"
+        c3(args, pg, gg, pt)
     else:
         small(args, pg, gg, pt)
     return 0
