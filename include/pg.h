@@ -203,6 +203,9 @@ typedef struct {
 #define PG_RUN_COUNT_BYTES 1  /* also count the merge-model bytes of every set operation */
 #define PG_RUN_NO_MODE_B 2    /* never count by complement (|A| - |A & B|) */
 #define PG_RUN_NO_TASK_BATCH 4  /* expand level 2 one root task at a time only */
+#define PG_RUN_LIGHT_KERNEL 8   /* run a long counting launch on the four-waves-per-SIMD build of
+                                   the kernel (128 VGPRs, no spills) instead of the five-wave one;
+                                   shorter launches always use it */
 
 typedef struct {
     double kernel_ms;        /* device time of the matching kernel (HIP events) */

@@ -537,7 +537,8 @@ void shape(const pg_graph *g, const pg_run_config *cfg, LaunchPlan &L, int mode,
     }
     // five waves per SIMD pay off on long counts that enumerate; shorter
     // launches measured faster at four (no spills)
-    const bool long_count = mode == pg::kModeCount && enums && L.n_et + L.n_vt >= kLongLaunchTasks;
+    const bool long_count = mode == pg::kModeCount && enums && L.n_et + L.n_vt >= kLongLaunchTasks &&
+                            !(cfg && (cfg->flags & PG_RUN_LIGHT_KERNEL));
     L.variant = L.with_av ? pg::kVarAV : pre ? pg::kVarPre : long_count ? pg::kVarPlain : pg::kVarLight;
     // persistent grid: exactly the wavefronts of this variant that can be
     // resident at once

@@ -65,6 +65,13 @@ def test_chunglu_100k_1m_six_motifs_batched(pg, orc):
     knobs = {k: v for k, v in rec["knobs"].items() if v}
     say(f"chunglu_100k_1m with the benchmark's knobs {knobs}")
     assert pg.count(G, plans, **knobs) == want
+    # both builds of the plain kernel: the long count launch takes the
+    # five-wave one (grid = its residency) unless the light one is asked for
+    c, st = pg.count_ex(G, plans)
+    assert c == want and st["grid_waves"] == G.resident_waves[0]
+    say("chunglu_100k_1m on the four-wave build of the kernel")
+    c, st = pg.count_ex(G, plans, flags=pg.PG_RUN_LIGHT_KERNEL)
+    assert c == want and st["grid_waves"] < G.resident_waves[0]
     say("chunglu_100k_1m triangle / wedge")
     assert pg.count(G, [pg.plan_pattern(pt.clique(3)), pg.plan_pattern(pt.star(3))]) == \
         [w["triangle"], w["sum_c_d_2"]]
