@@ -63,8 +63,11 @@ typedef struct {
     int32_t labelled;     /* 1 if vertex labels were given */
     int32_t device;       /* HIP device holding the graph */
     const int32_t *perm;  /* host, n entries: perm[rank] = original id; owned by the graph */
-    int32_t resident_waves[2]; /* wavefronts of the matching kernel resident at once on the device
-                                  (patterns without / with anti-vertices): the default grid */
+    int32_t resident_waves[2]; /* wavefronts of the matching kernel resident at once on the device:
+                                  [0] the build for long count launches, [1] the anti-vertex
+                                  build.  A launch's default grid is the residency of the build
+                                  it runs on (shorter and labelled launches use a four-wave build,
+                                  at most [0]) */
     int32_t hub_count;      /* rows held as bitmaps too (the hub_count highest ranks) */
     int32_t hub_min_degree; /* smallest degree among them (0 if none) */
 } pg_graph_info_t;
