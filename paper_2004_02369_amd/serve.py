@@ -5,7 +5,9 @@ them while launch slots and workspace memory are free:
 
 * every admitted batch is one asynchronous launch (``pg.submit``) on a stream
   of its own, with a grid of ``resident waves / slots`` wavefronts, so up to
-  ``slots`` launches run side by side;
+  ``slots`` launches run side by side; a heavy launch (by the cost policy)
+  holds ``slots - 1`` slots and their share of the grid, one at a time, so
+  one slot always stays for light requests and a heavy launch ends sooner;
 * count requests waiting in the queue are merged into one launch
   (continuous batching): their plans share one root frontier (Sec. 5.4),
   identical plans are counted once, up to 64 plans per launch;
@@ -119,6 +121,8 @@ class Batch:
     nbytes: int
     offset: int = -1
     slot: int = -1
+    extra_slots: list = field(default_factory=list)  # further slots a wide (heavy) launch holds
+    grid: int = 0
     job: object = None
     t_submit: float = 0.0
     heavy: bool = False
@@ -177,7 +181,7 @@ def next_batch(queue, size_of, pool: Pool, policy: Policy | None = None, allow_h
     behind it join its launch while the unique plans stay within 64 and the
     policy's cost cap holds (existence requests run alone and keep their
     place).  The launch is cut from the back until its workspace fits.
-    size_of(plans, kind) -> workspace bytes.  Returns (batch, rejected): a
+    size_of(plans, kind, heavy) -> workspace bytes.  Returns (batch, rejected): a
     Batch (its workspace already carved from the pool) or None when nothing
     can start now; and the head if it can never fit (larger than the whole
     pool), else None."""
@@ -213,7 +217,7 @@ def next_batch(queue, size_of, pool: Pool, policy: Policy | None = None, allow_h
             cost += add
     while True:
         plans, index = _merge(chosen)
-        nbytes = size_of(plans, head.query.kind)
+        nbytes = size_of(plans, head.query.kind, heavy)
         if len(chosen) == 1 and nbytes > pool.size:
             return None, head
         off = pool.alloc(nbytes)
@@ -270,8 +274,9 @@ class Server:
         self.grid = max(1, graph.resident_waves[0] // slots)
         self.time_limit_ms = time_limit_ms
         self.policy = policy or Policy()
-        # heavy launches may hold all slots but one, which stays for light ones
-        self.max_heavy = max(1, slots - 1)
+        # one heavy launch at a time holds all slots but one (and their share
+        # of the grid); the last slot stays for light ones
+        self.heavy_width = max(1, slots - 1)
         dev = f"cuda:{graph.device}"
         pool_bytes = -(-pool_bytes // ALIGN) * ALIGN
         self.streams = slot_streams(dev, slots)
@@ -290,14 +295,23 @@ class Server:
         self.merged_requests = 0
         self.log = []  # one record per finished launch
 
-    def size_of(self, plans, kind):
-        key = (tuple(id(p) for p in plans), kind)
-        b = self._sizes.get(key)
-        if b is None:
+    def launch_shape(self, plans, kind, heavy=False):
+        """(workspace bytes, grid) of a launch: a heavy one is wide unless its
+        wide workspace could never fit the pool."""
+        key = (tuple(id(p) for p in plans), kind, heavy)
+        r = self._sizes.get(key)
+        if r is None:
             mode = self.pg.PG_JOB_EXISTS if kind == "exists" else self.pg.PG_JOB_COUNT
-            b = self.pg.job_workspace_size(self.g, plans, mode, grid_waves=self.grid)
-            self._sizes[key] = b
-        return b
+            grid = self.grid * (self.heavy_width if heavy else 1)
+            b = self.pg.job_workspace_size(self.g, plans, mode, grid_waves=grid)
+            if grid != self.grid and b > self.pool.size:
+                grid = self.grid
+                b = self.pg.job_workspace_size(self.g, plans, mode, grid_waves=grid)
+            r = self._sizes[key] = (b, grid)
+        return r
+
+    def size_of(self, plans, kind, heavy=False):
+        return self.launch_shape(plans, kind, heavy)[0]
 
     def offer(self, req: Request):
         self.queue.append(req)
@@ -314,9 +328,15 @@ class Server:
             if b.job.done():
                 progress += self._retire(b)
         while self.free_slots and self.queue:
-            n_heavy = sum(1 for x in self.inflight if x.heavy)
-            b, rejected = next_batch(self.queue, self.size_of, self.pool, self.policy,
-                                     allow_heavy=n_heavy < self.max_heavy)
+            heavy_busy = any(x.heavy for x in self.inflight)
+            allow_heavy = not heavy_busy and len(self.free_slots) >= self.heavy_width
+            if not heavy_busy and not allow_heavy and self.policy.heavy(self.queue[0]):
+                # the oldest request is heavy and waits for its slots: light
+                # launches keep to the slots a heavy launch leaves free
+                n_light = sum(1 for x in self.inflight if not x.heavy)
+                if n_light >= self.slots - self.heavy_width:
+                    break
+            b, rejected = next_batch(self.queue, self.size_of, self.pool, self.policy, allow_heavy=allow_heavy)
             if rejected is not None:
                 self.queue.remove(rejected)
                 rejected.error = "workspace larger than the pool"
@@ -329,11 +349,15 @@ class Server:
             for r in b.requests:
                 self.queue.remove(r)
             b.slot = self.free_slots.pop()
+            _, b.grid = self.launch_shape(b.plans, b.kind, b.heavy)
+            if b.heavy:
+                for _ in range(min(len(self.free_slots), b.grid // self.grid - 1)):
+                    b.extra_slots.append(self.free_slots.pop())
             ws = self.mem[b.offset:b.offset + b.nbytes]
             mode = pg.PG_JOB_EXISTS if b.kind == "exists" else pg.PG_JOB_COUNT
             b.t_submit = time.perf_counter()
             try:
-                b.job = pg.submit(self.g, b.plans, ws, self.streams[b.slot], mode=mode, grid_waves=self.grid,
+                b.job = pg.submit(self.g, b.plans, ws, self.streams[b.slot], mode=mode, grid_waves=b.grid,
                                   time_limit_ms=self.time_limit_ms)
             except pg.PGError as e:
                 self._release(b)
@@ -355,6 +379,8 @@ class Server:
     def _release(self, b):
         self.pool.free(b.offset)
         self.free_slots.append(b.slot)
+        self.free_slots.extend(b.extra_slots)
+        b.extra_slots = []
 
     def _retire(self, b) -> int:
         err, st = None, {}
@@ -364,7 +390,7 @@ class Server:
         except self.pg.PGError as e:
             err, res = str(e), None
         t = time.perf_counter()
-        self.log.append({"launch": b.lid, "slot": b.slot, "kind": b.kind, "heavy": b.heavy,
+        self.log.append({"launch": b.lid, "slot": b.slot, "grid": b.grid, "kind": b.kind, "heavy": b.heavy,
                          "queries": sorted({r.query.name for r in b.requests}), "requests": len(b.requests),
                          "t_submit": b.t_submit, "t_done": t, "kernel_ms": st.get("kernel_ms"), "error": err})
         self.inflight.remove(b)

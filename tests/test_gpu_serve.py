@@ -197,6 +197,10 @@ def test_serving_alone_equals_in_mix(pg, g_mid):
     assert srv.merged_requests > 0          # continuous batching happened
     assert any(srv.policy.heavy(r) for r in reqs) and not all(srv.policy.heavy(r) for r in reqs)
     assert srv.pool.used == 0 and sorted(srv.free_slots) == [0, 1, 2]
+    # a launch runs on a slot's grid, or (heavy only) on the wide grid of
+    # the slots it holds; at most one heavy launch at a time
+    wide = [rec for rec in srv.log if rec["grid"] != srv.grid]
+    assert all(rec["heavy"] and rec["grid"] == srv.grid * srv.heavy_width for rec in wide)
     summ = serve.summarize(reqs, t0)
     say(f"mix: p50 {summ['p50_ms']:.2f} ms, p99 {summ['p99_ms']:.2f} ms, "
-        f"{summ['completed_qps']:.0f} QPS, {srv.launches} launches")
+        f"{summ['completed_qps']:.0f} QPS, {srv.launches} launches ({len(wide)} wide)")

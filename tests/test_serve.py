@@ -58,7 +58,7 @@ class FakePlan:
 
 def _size(per_plan=1000, base=ALIGN):
     # workspace grows with the deepest plan and the trie size
-    return lambda plans, kind: base + per_plan * len(plans) + 100000 * max(p.depth for p in plans)
+    return lambda plans, kind, heavy=False: base + per_plan * len(plans) + 100000 * max(p.depth for p in plans)
 
 
 def _q(name, kind="count", plans=None):
