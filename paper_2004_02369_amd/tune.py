@@ -11,7 +11,9 @@ The knobs (pg_run_config):
 * ``batch_max_avg`` -- a level whose children only count is expanded for up
   to 64 parents in one flattened pass while the parents average at most this
   many candidates, parent by parent otherwise (decided per batch);
-* ``flags`` -- PG_RUN_NO_TASK_BATCH turns the flattened pass off everywhere.
+* ``flags`` -- PG_RUN_NO_TASK_BATCH turns the flattened pass off everywhere;
+  PG_RUN_LIGHT_KERNEL runs a long count launch on the four-wave build of the
+  kernel instead of the five-wave one.
 
 The search is coordinate descent over measured kernel times (best of a few
 launches), each trial under a device time limit of a few times the best so
@@ -30,7 +32,7 @@ SPACE = {
     "hub_min_degree": [0, 32, 64, 128, 256, 1024, -1],
     "chunk": [4, 8, 16, 32, 64, 128],
     "batch_max_avg": [0, 8, 16, 32, 64, 128, 512],
-    "flags": [0, 4],  # 4 = PG_RUN_NO_TASK_BATCH
+    "flags": [0, 4, 8],  # 4 = PG_RUN_NO_TASK_BATCH, 8 = PG_RUN_LIGHT_KERNEL
 }
 DEFAULT = {"hub_min_degree": 0, "chunk": 0, "batch_max_avg": 0, "flags": 0}
 

@@ -58,4 +58,4 @@ def test_default_space_is_valid_launch_knobs():
     from paper_2004_02369_amd import pg
     assert set(tune.SPACE) <= set(pg.RUN_KNOBS) and set(tune.DEFAULT) == set(tune.SPACE)
     assert 0 in tune.SPACE["hub_min_degree"] and -1 in tune.SPACE["hub_min_degree"]
-    assert tune.SPACE["flags"] == [0, pg.PG_RUN_NO_TASK_BATCH]
+    assert tune.SPACE["flags"] == [0, pg.PG_RUN_NO_TASK_BATCH, pg.PG_RUN_LIGHT_KERNEL]
