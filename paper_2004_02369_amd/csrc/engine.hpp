@@ -52,10 +52,10 @@ struct KParams {
     long long task_end;
 };
 
-// Kernel variants: plain (long count launches, five waves per SIMD);
+// Kernel variants: plain (long count launches; 96 VGPRs, 18 waves per CU);
 // "pre" for labelled roots, domain marks or factor nodes (roots are
 // filtered before their rows load); anti-vertex checks; light (the plain
-// program at four waves per SIMD, for launches that end quickly).
+// program at 128 VGPRs, 16 waves per CU, for launches that end quickly).
 enum Variant : int { kVarPlain = 0, kVarPre = 1, kVarAV = 2, kVarLight = 3 };
 constexpr int kNumVariants = 4;
 
