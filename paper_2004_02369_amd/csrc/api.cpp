@@ -95,6 +95,11 @@ struct pg_graph {
     std::vector<int64_t> hub_deg;  // host: degrees of ranks hub_start..n-1 (ascending)
     int64_t hub_words = 0;
     int16_t *lab = nullptr;
+    // labelled graphs: col holds, after the 2m row entries, a copy of every
+    // row sorted by (label, id) at the same offsets; lab_off[v * (n_labels
+    // + 1) + l] is where label l starts within v's row of that copy
+    int32_t *lab_off = nullptr;
+    int32_t n_labels = 0;
     int32_t *dperm = nullptr;
     int32_t *tsrc = nullptr;
     int32_t *tdst = nullptr;
@@ -127,6 +132,7 @@ struct pg_graph {
         dfree(up);
         dfree(hub_bits);
         dfree(lab);
+        dfree(lab_off);
         dfree(dperm);
         dfree(tsrc);
         dfree(tdst);
@@ -155,6 +161,8 @@ namespace {
 constexpr int64_t kHubMinDegree = 16;
 constexpr long long kArenaInts = 32768;  // per wavefront
 constexpr int64_t kHubBudgetBytes = int64_t(1) << 30;
+// label-sorted row copy: at most this many label offsets (4 bytes each)
+constexpr int64_t kLabelOffsetBudget = int64_t(1) << 28;
 
 constexpr int kCtlCounts = 0;
 constexpr int kCtlCursor = 64;
@@ -348,7 +356,35 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         for (int v = 0; v < pg::kNumVariants; v++) g->blocks_per_cu[v] = pg::match_blocks_per_cu(v);
         pg_status st;
         if ((st = upload(&g->rp, rp, &g->device_bytes))) return st;
-        if ((st = upload(&g->col, col, &g->device_bytes))) return st;
+        // labelled levels drive from the part of a row that holds their
+        // label: each row again, sorted by (label, id), after the rows
+        // (so one 32-bit offset into col addresses both), and per vertex
+        // the start of every label's part
+        int32_t n_labels = 0;
+        if (labels && 4 * mu <= (int64_t)INT32_MAX) {
+            for (int16_t l : lab) n_labels = std::max<int32_t>(n_labels, l + 1);
+            if ((int64_t)n * (n_labels + 1) > kLabelOffsetBudget) n_labels = 0;
+        }
+        if (n_labels > 0) {
+            const int32_t stride = n_labels + 1;
+            std::vector<int32_t> ext((size_t)(4 * mu));
+            std::copy(col.begin(), col.end(), ext.begin());
+            std::vector<int32_t> off((size_t)n * (size_t)stride, 0);
+            for (int32_t r = 0; r < n; r++) {
+                int32_t *o = off.data() + (size_t)r * (size_t)stride;
+                for (int64_t e = rp[r]; e < rp[r + 1]; e++) o[lab[col[e]] + 1]++;
+                for (int32_t l = 0; l < n_labels; l++) o[l + 1] += o[l];
+                std::vector<int32_t> pos(o, o + n_labels);
+                // the row is in id order, so a stable placement by label
+                // leaves every label's part in id order
+                for (int64_t e = rp[r]; e < rp[r + 1]; e++) ext[(size_t)(2 * mu + rp[r] + pos[lab[col[e]]]++)] = col[e];
+            }
+            if ((st = upload(&g->col, ext, &g->device_bytes))) return st;
+            if ((st = upload(&g->lab_off, off, &g->device_bytes))) return st;
+            g->n_labels = n_labels;
+        } else if ((st = upload(&g->col, col, &g->device_bytes))) {
+            return st;
+        }
         if ((st = upload(&g->up, up, &g->device_bytes))) return st;
         // hub rows also as dense bitmaps: the highest-degree vertices (rank
         // order is degree order) with degree >= hub_min, within a budget
@@ -572,7 +608,10 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     std::memset(&P, 0, sizeof(P));
     P.rp = g->rp;
     P.col = g->col;
-    P.ncol = 2 * g->m;
+    P.ncol = (g->n_labels > 0 ? 4 : 2) * g->m;
+    P.lab_off = g->lab_off;
+    P.n_labels = g->n_labels;
+    P.lab_copy = 2 * g->m;
     P.up = g->up;
     // bitmaps are held for ranks hub_start..n-1 (degree order); a launch may
     // use them from a later rank on, binary search below it

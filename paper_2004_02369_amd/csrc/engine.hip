@@ -285,6 +285,31 @@ struct Ctx {
         return e > b ? e - b : 0;
     }
 
+    // The candidates of a level with a fixed label, drawn from y's row: in
+    // the variant for labelled plans, the part of the row's label-sorted
+    // copy that holds the label (id order, so ranges restrict as usual;
+    // no owner, so no bitmap and no owner split)
+    __device__ __forceinline__ RowRef drow(const Node &N, int y, int l) const {
+        RowRef r = row(y, l);
+        if constexpr (kFac) {
+            if (N.label >= 0 && P.lab_off) {
+                RowRef s;
+                s.up = 0;
+                s.owner = -1;
+                s.p = r.p + P.lab_copy;
+                s.n = 0;
+                if (N.label < P.n_labels) {
+                    const int32_t *o = P.lab_off + (long long)r.owner * (P.n_labels + 1);
+                    const int32_t a = o[N.label];
+                    s.p += a;
+                    s.n = o[N.label + 1] - a;
+                }
+                return s;
+            }
+        }
+        return r;
+    }
+
     __device__ __forceinline__ RowRef vrow(int32_t v) const {
         RowRef r;
         long long o = P.rp[v];
@@ -337,7 +362,7 @@ struct Ctx {
         }
         for (uint32_t s = N.t_isect; s; s &= s - 1) {
             int y = __builtin_ctz(s);
-            RowRef r = row(y, -1);
+            RowRef r = drow(N, y, -1);
             int32_t n;
             int32_t b = restrict_row(r, lo, hi, &n);
             bytes += n;
@@ -419,7 +444,7 @@ struct Ctx {
             }
             for (uint32_t s = N.t_isect; s; s &= s - 1) {
                 const int y = __builtin_ctz(s);
-                RowRef r = row(y, l);
+                RowRef r = drow(N, y, l);
                 int32_t n;
                 int32_t b = restrict_row(r, lo, hi, &n);
                 bytes += n;
@@ -835,7 +860,7 @@ struct Ctx {
             }
             for (uint32_t s = E.t_isect; s; s &= s - 1) {
                 const int y = __builtin_ctz(s);
-                RowRef r = row(y, lane);
+                RowRef r = drow(E, y, lane);
                 int32_t n;
                 const int32_t b = restrict_row(r, lo, hi, &n);
                 bytes += n;

@@ -50,6 +50,12 @@ struct KParams {
     long long mark_words;
     long long task_begin;      // root tasks [task_begin, task_end) of this launch; task_end 0 = to the last
     long long task_end;
+    // labelled graphs: col[lab_copy + rp[v] ..) is v's row sorted by (label,
+    // id); label l's part starts lab_off[v * (n_labels + 1) + l] entries in
+    // (nullptr / 0 = no copy)
+    const int32_t *lab_off;
+    int32_t n_labels;
+    long long lab_copy;
 };
 
 // Kernel variants: plain (long count launches; 96 VGPRs, 18 waves per CU);
