@@ -459,8 +459,13 @@ struct Ctx {
             const int npos = (N.base >= 0 ? 1 : 0) + __builtin_popcount(N.t_isect);
             const int ndiff = __builtin_popcount(N.t_diff);
             bool complement = false;
-            if (!emit && npos == 1 && N.label < 0 && N.av_count == 0 && ndiff >= 1 && ndiff <= kMaxDiffB &&
-                !(P.run_flags & PG_RUN_NO_MODE_B) && dlen > 0) {
+            // labelled plans: a label part as the positive operand already
+            // holds only candidates with the label, and with no difference
+            // rows the count is |P| less the excluded images in it
+            const bool lab_part = kFac && N.label >= 0 && P.lab_off && drv != kBaseOp;
+            if (!emit && npos == 1 && (N.label < 0 || lab_part) && N.av_count == 0 &&
+                (ndiff >= 1 || (kFac && ndiff == 0)) && ndiff <= kMaxDiffB && !(P.run_flags & PG_RUN_NO_MODE_B) &&
+                dlen > 0) {
                 // restricted difference rows become the complement's segments
                 int k = 0;
                 for (uint32_t s = N.t_diff; s; s &= s - 1, k++) {
@@ -506,7 +511,7 @@ struct Ctx {
                 }
                 // direct: every element of P is probed against each D; by
                 // complement: an element of D_k against P and D_0..D_k-1
-                complement = (long long)sl0 + 2ll * sl1 + 3ll * sl2 < (long long)ndiff * dlen;
+                complement = (kFac && ndiff == 0) || (long long)sl0 + 2ll * sl1 + 3ll * sl2 < (long long)ndiff * dlen;
             }
             if (P.run_flags & PG_RUN_COUNT_BYTES) {
                 for (uint32_t s = N.t_diff; s; s &= s - 1) {
