@@ -5,6 +5,7 @@
                                                      # 21 induced 5-motifs + K5, batched vs one launch each
     python -m paper_2004_02369_amd.measure small     # launch-bound case: ER 2k/20k, batched vs singles
     python -m paper_2004_02369_amd.measure inversion # induced census via non-induced counts + inversion
+    python -m paper_2004_02369_amd.measure c1        # triangle, wedge, K4 on ER 2k/20k, one pattern per launch
     python -m paper_2004_02369_amd.measure c3        # 21 induced 5-motifs + K5 on R-MAT scale 20 (16M edges):
                                                      # each alone under a time limit, the finishing ones batched
 """
@@ -86,6 +87,27 @@ def inversion(args, pg, gg, pt):
                           "inversion_s": best, "speedup": t_direct / best, "equal": inv == direct}), flush=True)
 
 
+def c1(args, pg, gg, pt):
+    """Triangle, wedge and 4-clique counts on ER 2k/20k, one pattern per
+    launch: kernel time (best of several launches), host-side latency of
+    the synchronous call, and matches/s."""
+    G = pg.load_graph(*gg.workload("er_2k_20k"), device=0)
+    import torch
+    s = torch.cuda.current_stream(0)
+    for name, spec in (("triangle", pt.clique(3)), ("wedge", pt.star(3)), ("K4", pt.clique(4))):
+        plan = pg.plan_pattern(spec)
+        best_k, best_t, count = float("inf"), float("inf"), None
+        for _ in range(30):
+            t0 = time.perf_counter()
+            c, st = pg.count_ex(G, [plan], stream=s)
+            best_t = min(best_t, time.perf_counter() - t0)
+            best_k = min(best_k, st["kernel_ms"])
+            count = c[0]
+        print(json.dumps({"measure": "c1", "workload": "er_2k_20k", "pattern": name, "count": count,
+                          "kernel_ms": best_k, "call_ms": best_t * 1e3,
+                          "matches_per_s": count / (best_k / 1e3)}), flush=True)
+
+
 def c3(args, pg, gg, pt):
     """The 22-plan family (21 induced 5-motifs + K5) at full size: each plan
     alone under a device time limit, then every plan that finished in one
@@ -151,7 +173,7 @@ def small(args, pg, gg, pt):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion", "c3"])
+    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion", "c1", "c3"])
     ap.add_argument("--workload", default=None)
     ap.add_argument("--limit-ms", type=int, default=600000)
     ap.add_argument("--tune-budget", type=float, default=60.0)
@@ -169,6 +191,8 @@ def main(argv=None):
         motifs5(args, pg, gg, pt)
     elif args.what == "inversion":
         inversion(args, pg, gg, pt)
+    elif args.what == "c1":
+        c1(args, pg, gg, pt)
     elif args.what == "c3":
         args.workload = args.workload or "rmat20_16m"
         c3(args, pg, gg, pt)
