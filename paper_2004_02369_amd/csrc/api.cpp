@@ -556,6 +556,8 @@ pg_status check_args(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, 
 // root tasks from which a count launch with enumeration levels takes the
 // five-wave kernel variant
 constexpr long long kLongLaunchTasks = 1ll << 18;
+// small launches: root tasks (times program leaves) per wave of the grid
+constexpr long long kTasksPerWave = 64;
 
 // shape of a launch for a built trie (mode: pg::RunMode; marks: domain
 // bitmaps are on)
@@ -576,9 +578,16 @@ void shape(const pg_graph *g, const pg_run_config *cfg, LaunchPlan &L, int mode,
     const bool long_count = mode == pg::kModeCount && enums && L.n_et + L.n_vt >= kLongLaunchTasks &&
                             !(cfg && (cfg->flags & PG_RUN_LIGHT_KERNEL));
     L.variant = L.with_av ? pg::kVarAV : pre ? pg::kVarPre : long_count ? pg::kVarPlain : pg::kVarLight;
-    // persistent grid: exactly the wavefronts of this variant that can be
-    // resident at once
-    L.grid = cfg && cfg->grid_waves ? cfg->grid_waves : g->n_cu * g->blocks_per_cu[L.variant];
+    // persistent grid: the wavefronts of this variant that can be resident
+    // at once, fewer for small launches (about kTasksPerWave root tasks per
+    // program leaf and wave, at least one wave per CU): there, starting and
+    // draining idle waves costs more than the matching
+    long long leaves = 0;
+    for (const pg::Node &n : T.nodes) leaves += (n.kind == pg::kCount || n.kind == pg::kEmit) ? 1 : 0;
+    const long long resident = (long long)g->n_cu * g->blocks_per_cu[L.variant];
+    const long long want = ((L.n_et + L.n_vt) * std::max(1ll, leaves) + kTasksPerWave - 1) / kTasksPerWave;
+    L.grid = cfg && cfg->grid_waves ? cfg->grid_waves
+                                    : (int)std::min(resident, std::max<long long>(g->n_cu, want));
     L.chunk = cfg && cfg->chunk ? cfg->chunk : 64;
     // scratch: one set per enumeration level (levels 2 .. max_level-2) plus
     // the arena of batched expansions
