@@ -187,7 +187,9 @@ pg_status pg_plan_programs(const pg_plan *plan, int32_t enum_mode, int32_t *buf,
 /* ---------------------------------------------------------------- counting */
 
 typedef struct {
-    int32_t grid_waves;    /* persistent wavefronts; 0 = auto (CUs x waves per CU) */
+    int32_t grid_waves;    /* persistent wavefronts; 0 = auto: the resident wavefronts of the
+                              kernel build the launch runs on, fewer for small launches (about
+                              64 root tasks per program leaf per wave, at least one per CU) */
     int32_t chunk;         /* root tasks claimed per atomic; 0 = auto */
     int32_t flags;         /* PG_RUN_* */
     int32_t time_limit_ms; /* stop every wavefront once this long has passed on the device clock
