@@ -81,6 +81,9 @@ def _L():
         lib.orc_noninduced4.restype = ctypes.c_int
         lib.orc_noninduced4.argtypes = [vp, ctypes.c_int, vp, vp]
         lib.orc_triangles_per_vertex.argtypes = [vp, vp]
+        lib.orc_edge_triangles.argtypes = [vp, ctypes.c_int, vp]
+        lib.orc_exists.restype = ctypes.c_int
+        lib.orc_exists.argtypes = [vp, ctypes.POINTER(_Pattern), ctypes.c_int]
         lib.orc_domains.restype = ctypes.c_int
         lib.orc_domains.argtypes = [vp, ctypes.POINTER(_Pattern), ctypes.c_int, vp, vp]
         _lib = lib
@@ -226,6 +229,15 @@ def count(g: Graph, spec, threads: int | None = None) -> int:
     if rc == -3:
         raise AssertionError("valid-map count not divisible by |Aut|")
     return (hi.value << 64) | lo.value
+
+
+def exists(g: Graph, spec, threads: int | None = None) -> bool:
+    """Whether the pattern has at least one match (Sec. 3.2.2): a search for
+    one valid map, stopped at the first found."""
+    rc = _L().orc_exists(g._h, ctypes.byref(_to_struct(spec)), threads or default_threads())
+    if rc < 0:
+        raise ValueError("pattern is not connected by true edges")
+    return rc == 1
 
 
 def domains(g: Graph, spec, threads: int | None = None, members: bool = False):
@@ -410,3 +422,77 @@ def star_row_invariant(k: int, induced_counts: dict[int, int]) -> int:
     c = spanning_copies(k)
     star = canonical_of_edges(k, [(0, i) for i in range(1, k)])
     return sum(c.get((star, q), 0) * induced_counts[q] for q in induced_counts)
+
+
+# ------------------------------------------- 5-vertex non-induced closed forms
+#
+# Counts of (not necessarily induced) subgraphs of a few 5-vertex shapes,
+# each from degrees and per-edge triangle counts.  With the spanning-copy
+# coefficients c(P, Q) they give exact linear checks on a vertex-induced
+# 5-motif census: N(P) = sum_Q c(P, Q) I(Q) (Sec. 3.1.3 relates the two
+# kinds of matches).  Shapes as edge lists:
+FIVE_NONINDUCED = {
+    "star4": [(0, 1), (0, 2), (0, 3), (0, 4)],
+    "fork": [(0, 1), (0, 2), (0, 3), (1, 4)],
+    "cricket": [(0, 1), (0, 2), (1, 2), (0, 3), (0, 4)],
+    "bull": [(0, 1), (0, 2), (1, 2), (0, 3), (1, 4)],
+    "book3": [(0, 1), (0, 2), (1, 2), (0, 3), (1, 3), (0, 4), (1, 4)],
+}
+
+
+def edge_triangles(g: Graph, threads: int | None = None):
+    """(off, adj, t): the oracle's CSR and, per adjacency slot, the number of
+    triangles through that edge."""
+    off, adj = g.csr()
+    t = np.zeros(max(1, len(adj)), dtype=np.int64)
+    _L().orc_edge_triangles(g._h, threads or default_threads(), t.ctypes.data)
+    return off, adj, t[: len(adj)]
+
+
+def noninduced5_closed_forms(g: Graph, threads: int | None = None) -> dict[str, int]:
+    """Subgraph counts of the FIVE_NONINDUCED shapes, exact (Python ints):
+
+    * star4:   sum_v C(d_v, 4)  (centre and an unordered 4-set of its neighbours)
+    * fork:    sum over ordered edges (c, x) of
+               (d_x - 1 - t_cx) C(d_c - 1, 2) + t_cx C(d_c - 2, 2)
+               (c the degree-3 vertex, x its neighbour of degree 2; x's other
+               neighbour w, then two more neighbours of c besides x and w)
+    * cricket: sum_v t_v C(d_v - 2, 2)  (the degree-4 vertex, one of its
+               triangles, two more of its neighbours)
+    * bull:    sum over edges {a, b} of t_ab ((d_a - 2)(d_b - 2) - (t_ab - 1))
+               (the triangle's edge that carries both pendants, the third
+               triangle vertex, then a pendant on each end; the two pendants
+               must differ, and they coincide exactly on another common
+               neighbour of a and b)
+    * book3:   sum over edges of C(t_ab, 3)  (the spine and three pages)
+    """
+    off, adj, t = edge_triangles(g, threads)
+    n = g.n
+    deg = np.diff(off).astype(np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), deg)
+    dc = [int(x) for x in deg]
+    out = {"star4": 0, "fork": 0, "cricket": 0, "bull": 0, "book3": 0}
+    tv = [0] * n
+    for v, x, te in zip(src.tolist(), adj.tolist(), t.tolist()):
+        tv[v] += te
+        dv, dx = dc[v], dc[x]
+        # ordered (c = v, x)
+        out["fork"] += (dx - 1 - te) * math.comb(dv - 1, 2) + te * math.comb(max(dv - 2, 0), 2)
+        if v < x:
+            out["bull"] += te * ((dv - 2) * (dx - 2) - (te - 1)) if te else 0
+            out["book3"] += math.comb(te, 3)
+    for v in range(n):
+        out["star4"] += math.comb(dc[v], 4)
+        out["cricket"] += (tv[v] // 2) * math.comb(max(dc[v] - 2, 0), 2)
+    return out
+
+
+def noninduced5_rows(induced_counts: dict[int, int]) -> dict[str, int]:
+    """sum_Q c(P, Q) I(Q) for each FIVE_NONINDUCED shape P, from a vertex-
+    induced 5-motif census keyed by canonical bitmask."""
+    c = spanning_copies(5)
+    out = {}
+    for name, edges in FIVE_NONINDUCED.items():
+        p = canonical_of_edges(5, edges)
+        out[name] = sum(c.get((p, q), 0) * cnt for q, cnt in induced_counts.items())
+    return out

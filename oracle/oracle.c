@@ -442,6 +442,60 @@ int orc_domains(const orc_graph *g, const orc_pattern *p, int nthreads, int64_t 
     return 0;
 }
 
+/* exists(G, p): is there at least one valid map (Sec. 3.2.2, existence
+ * queries)?  The same search as the valid-map count, from every start
+ * vertex in turn, ending at the first valid map any thread finds.  Returns
+ * 1 / 0, or -1 for a disconnected pattern. */
+typedef struct {
+    match_job J;
+    atomic_int found;
+} exists_job;
+
+static void *exists_worker(void *arg) {
+    exists_job *E = arg;
+    match_job *J = &E->J;
+    const orc_pattern *p = J->p;
+    int32_t img[16];
+    while (!atomic_load(&E->found)) {
+        int64_t v = atomic_fetch_add(&J->cursor, 1);
+        if (v >= J->g->n) break;
+        int u0 = J->order[0];
+        if (p->label[u0] != -1 && (!J->g->label || J->g->label[v] != p->label[u0])) continue;
+        img[u0] = (int32_t)v;
+        if (exists_rec(J, img, 1)) atomic_store(&E->found, 1);
+    }
+    return NULL;
+}
+
+int orc_exists(const orc_graph *g, const orc_pattern *p, int nthreads) {
+    exists_job E;
+    memset(&E, 0, sizeof(E));
+    E.J.g = g;
+    E.J.p = p;
+    int seen[16] = {0};
+    int head = 0, tail = 0;
+    E.J.order[tail++] = 0;
+    seen[0] = 1;
+    E.J.parent[0] = -1;
+    while (head < tail) {
+        int x = E.J.order[head++];
+        for (int y = 0; y < p->k; y++)
+            if ((p->edge[x] >> y & 1u) && !seen[y]) {
+                seen[y] = 1;
+                E.J.parent[tail] = head - 1;
+                E.J.order[tail++] = y;
+            }
+    }
+    if (tail != p->k) return -1;
+    atomic_init(&E.J.cursor, 0);
+    atomic_init(&E.found, 0);
+    int nt = nthreads < 1 ? 1 : (nthreads > 256 ? 256 : nthreads);
+    pthread_t th[256];
+    for (int t = 0; t < nt; t++) pthread_create(&th[t], NULL, exists_worker, &E);
+    for (int t = 0; t < nt; t++) pthread_join(th[t], NULL);
+    return atomic_load(&E.found) ? 1 : 0;
+}
+
 /* count(G, p) = |valid maps| / |Aut_t(p)|.  Returns 0 on success, -1 for a
  * disconnected pattern, -2 if |Aut_t| is out of the exhaustive range, -3 if
  * the division is not exact (which would mean a bug in this file). */
@@ -642,6 +696,20 @@ static void *codeg_worker(void *arg) {
     free(cnt);
     free(touched);
     return NULL;
+}
+
+/* t[e] = triangles through the edge in adjacency slot e (common neighbours
+ * of its two endpoints, counted by a merge of their sorted rows). */
+void orc_edge_triangles(const orc_graph *g, int nthreads, int64_t *t) {
+    cf_job J;
+    memset(&J, 0, sizeof(J));
+    J.g = g;
+    J.t_edge = t;
+    atomic_init(&J.cursor, 0);
+    int nt = nthreads < 1 ? 1 : (nthreads > 256 ? 256 : nthreads);
+    pthread_t th[256];
+    for (int i = 0; i < nt; i++) pthread_create(&th[i], NULL, tri_worker, &J);
+    for (int i = 0; i < nt; i++) pthread_join(th[i], NULL);
 }
 
 /* out[0..5] (each as lo/hi uint64 pairs in out_lo/out_hi):

@@ -1,6 +1,7 @@
 """Build libpg.so (HIP for gfx950 + host C++) in-tree with hipcc."""
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -31,12 +32,17 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
+    def compile_one(src):
         path = os.path.join(CSRC, src)
         obj = os.path.join(objdir, src + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        out = _run([HIPCC, *COMMON, *DEVICE, *lang, "-c", path, "-o", obj])
+        return obj, _run([HIPCC, *COMMON, *DEVICE, *lang, "-c", path, "-o", obj])
+
+    # the sources compile independently: one hipcc per source, side by side
+    with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        results = list(ex.map(compile_one, SOURCES))
+    objs = []
+    for obj, out in results:
         if verbose and out:
             print(out)
         objs.append(obj)

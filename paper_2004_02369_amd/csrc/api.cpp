@@ -659,6 +659,14 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.n = g->n;
     P.n_roots = (int32_t)L.trie.roots.size();
     P.chunk = L.chunk;
+    {
+        // claims grow from 1 task to `chunk` over the window's costliest
+        // tasks: claim j holds 1 + j / ramp tasks, and the growth spans the
+        // window when ramp = 2 span / (chunk (chunk - 1))
+        const long long span = la.task_end > 0 ? la.task_end - la.task_begin : L.n_et + L.n_vt;
+        const long long c = std::max(1, L.chunk);
+        P.chunk_ramp = c > 1 ? std::max(1ll, 2 * span / (c * (c - 1))) : 1;
+    }
     P.n_plans = n_plans;
     P.mode = la.mode;
     P.run_flags = cfg ? cfg->flags : 0;

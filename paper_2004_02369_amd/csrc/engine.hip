@@ -135,19 +135,36 @@ __device__ __forceinline__ int32_t restrict_row(const RowRef &r, int32_t lo, int
     return b;
 }
 
+// C(n, j) exactly.  After step t, r = C(n - j + t, t); the product r * f is
+// formed in 128 bits, so only a result of 2^64 or more sets the flag (the
+// quotient of each step is an integer, C(n-j+t, t) = C(n-j+t-1, t-1) * f / t).
 __device__ __forceinline__ unsigned long long choose(unsigned long long n, int j, bool *ovf) {
     if ((long long)j > (long long)n) return 0;
     unsigned long long r = 1;
     for (int t = 1; t <= j; t++) {
-        unsigned long long f = n - (unsigned long long)j + (unsigned long long)t;
-        unsigned long long q;
-        if (__builtin_mul_overflow(r, f, &q)) {
+        const unsigned long long f = n - (unsigned long long)j + (unsigned long long)t;
+        const unsigned __int128 q = (unsigned __int128)r * f / (unsigned __int128)t;
+        if (q >> 64) {
             *ovf = true;
             return 0;
         }
-        r = q / (unsigned long long)t;
+        r = (unsigned long long)q;
     }
     return r;
+}
+
+// First task of claim i: claims hold 1 + floor(j / ramp) tasks (claim j),
+// capped at `chunk`, so they grow linearly over the costliest tasks and
+// stay at `chunk` after that.  With q = floor(i / ramp), r = i mod ramp the
+// sum of the first i sizes is i + ramp q (q - 1) / 2 + r q while q < chunk.
+__device__ __forceinline__ long long claim_start(long long i, int chunk, long long ramp) {
+    const long long full = ramp * (long long)(chunk - 1);  // claims before the cap is reached
+    if (i <= full) {
+        const long long q = i / ramp, r = i - (i / ramp) * ramp;
+        return i + ramp * (q * (q - 1) / 2) + r * q;
+    }
+    const long long q = chunk - 1;
+    return full + ramp * (q * (q - 1) / 2) + (i - full) * (long long)chunk;
 }
 
 // exclusive prefix sum over the wave; *tot receives the wave total
@@ -1257,23 +1274,22 @@ __device__ __forceinline__ void match_body(const KParams P) {
     // followed by the vertex tasks
     const long long t_lo = P.task_begin;
     const long long t_hi = P.task_end > 0 ? P.task_end : P.n_etasks + P.n_vtasks;
-    const long long span = t_hi - t_lo;
     for (;;) {
         if (C.stopped()) break;
-        // guided claiming: tasks are sorted costliest first, so the chunk
-        // grows linearly from 1 at the head to P.chunk at the tail (the
-        // chunk is sized from a possibly stale cursor; any size is correct)
-        unsigned long long t0 = 0;
-        long long chunk = 1;
+        // guided claiming: tasks are sorted costliest first, so claims grow
+        // from one task at the head to P.chunk at the tail.  The cursor
+        // counts claims; claim i covers a fixed range of tasks (a function
+        // of i alone), so every launch forms the same task batches.
+        long long c_beg = 0, c_end = 0;
         if (lane == 0) {
-            const long long pos = (long long)__atomic_load_n(P.cursor, __ATOMIC_RELAXED);
-            chunk = 1 + (span > 0 ? (min(pos, span) * (long long)(P.chunk - 1)) / span : 0);
-            t0 = (unsigned long long)t_lo + atomicAdd(P.cursor, (unsigned long long)chunk);
+            const long long i = (long long)atomicAdd(P.cursor, 1ull);
+            c_beg = claim_start(i, P.chunk, P.chunk_ramp);
+            c_end = claim_start(i + 1, P.chunk, P.chunk_ramp);
         }
-        t0 = __shfl(t0, 0);
-        chunk = __shfl(chunk, 0);
-        if ((long long)t0 >= t_hi) break;
-        const long long c_end = min((long long)t0 + chunk, t_hi);
+        c_beg = t_lo + (long long)__shfl(c_beg, 0);
+        c_end = min(t_lo + (long long)__shfl(c_end, 0), t_hi);
+        if (c_beg >= t_hi) break;
+        const long long t0 = c_beg;
         for (long long tb = (long long)t0; tb < c_end;) {
             // edge tasks occupy [0, n_etasks), vertex tasks the rest; a chunk
             // may straddle the boundary

@@ -41,7 +41,8 @@ struct KParams {
     long long time_budget;     // wall-clock ticks from the first wavefront's start; 0 = unlimited
     int32_t n;
     int32_t n_roots;
-    int32_t chunk;
+    int32_t chunk;             // largest claim of root tasks
+    long long chunk_ramp;      // claims per step of claim growth (claim j holds 1 + j / chunk_ramp tasks, at most chunk)
     int32_t n_plans;
     int32_t mode;
     int32_t run_flags;

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "erdos_renyi_m", "chung_lu", "rmat", "gnp", "complete", "complete_multipartite",
     "cycle", "path", "star", "petersen", "turan", "disjoint_union", "dirty_copy",
-    "relabel", "all_graphs", "WORKLOADS", "workload", "labelled_workload",
+    "relabel", "all_graphs", "hub_plus_er", "WORKLOADS", "workload", "labelled_workload",
 ]
 
 
@@ -199,6 +199,16 @@ def disjoint_union(*graphs):
         vs.append(v.astype(np.int64) + off)
         off += n
     return off, np.concatenate(us).astype(np.int32), np.concatenate(vs).astype(np.int32)
+
+
+def hub_plus_er(n_leaves: int, m_leaves: int, seed: int = 5):
+    """One hub adjacent to every other vertex (vertex 0, degree n_leaves)
+    plus G(n_leaves, m_leaves) among the leaves (vertices 1..n_leaves)."""
+    _, u, v = erdos_renyi_m(n_leaves, m_leaves, seed=seed)
+    leaves = np.arange(1, n_leaves + 1, dtype=np.int32)
+    src = np.concatenate([np.zeros(n_leaves, np.int32), u + 1])
+    dst = np.concatenate([leaves, v + 1])
+    return n_leaves + 1, src.astype(np.int32), dst.astype(np.int32)
 
 
 def relabel(graph, seed: int):

@@ -8,6 +8,8 @@
     python -m paper_2004_02369_amd.measure c1        # triangle, wedge, K4 on ER 2k/20k, one pattern per launch
     python -m paper_2004_02369_amd.measure c3        # 21 induced 5-motifs + K5 on R-MAT scale 20 (16M edges):
                                                      # each alone under a time limit, the finishing ones batched
+    python -m paper_2004_02369_amd.measure c5        # the serving catalogue's count queries on R-MAT scale 22
+                                                     # (64M edges): each alone (time, merge-model bytes), then batched
 """
 from __future__ import annotations
 
@@ -150,6 +152,50 @@ def c3(args, pg, gg, pt):
     print(json.dumps(out), flush=True)
 
 
+def c5(args, pg, gg, pt):
+    """Every count query of the serving catalogue on the serving graph, alone
+    under a device time limit: kernel time, count and merge-model bytes
+    (a separate counting run); then the finishing ones in one launch."""
+    from . import serve
+    t0 = time.perf_counter()
+    G = pg.load_graph(*gg.workload(args.workload), device=0)
+    _say(f"{args.workload}: n={G.n} m={G.m} d_max={G.d_max} ready in {time.perf_counter() - t0:.1f} s")
+    seen, rows = {}, []
+    for name, kind, specs in serve.catalogue_specs(pt):
+        if kind != "count":
+            continue
+        key = serve.pattern_key(specs[0])
+        if key in seen:
+            continue
+        plan = pg.plan_pattern(specs[0])
+        seen[key] = plan
+        rec = {"name": name, "edges": specs[0]["edges"], "induced": bool(specs[0].get("induced")),
+               "anti": specs[0].get("anti")}
+        try:
+            c, st = pg.count_ex(G, [plan], time_limit_ms=args.limit_ms)
+            rec.update(ms=st["kernel_ms"], count=c[0], grid=st["grid_waves"])
+            c2, st2 = pg.count_ex(G, [plan], flags=pg.PG_RUN_COUNT_BYTES, time_limit_ms=4 * args.limit_ms)
+            assert c2 == c
+            rec["logical_bytes"] = st2["logical_bytes"]
+        except pg.PGError as e:
+            if e.status not in (pg.PG_ETIMEDOUT, pg.PG_EOVERFLOW):
+                raise
+            rec.update(ms=None, count=None, error=pg._STATUS.get(e.status))
+        rec["plan"] = plan
+        rows.append(rec)
+        _say(f"{name}: {rec.get('ms')} ms, count {rec.get('count')}, bytes {rec.get('logical_bytes')}")
+    done = [r for r in rows if r["ms"] is not None]
+    out = {"measure": "c5", "workload": args.workload, "n": G.n, "m": G.m, "d_max": G.d_max,
+           "limit_ms": args.limit_ms, "queries": [{k: v for k, v in r.items() if k != "plan"} for r in rows]}
+    if done:
+        c, st = pg.count_ex(G, [r["plan"] for r in done])
+        assert c == [r["count"] for r in done], "batched counts differ from the single launches"
+        out["batched_ms"] = st["kernel_ms"]
+        out["singles_sum_ms"] = sum(r["ms"] for r in done)
+        out["batched_speedup"] = out["singles_sum_ms"] / st["kernel_ms"]
+    print(json.dumps(out), flush=True)
+
+
 def small(args, pg, gg, pt):
     """Launch-bound regime: the six induced 4-motifs on ER 2k/20k, one
     batched launch against six launches, best of several repetitions."""
@@ -173,7 +219,7 @@ def small(args, pg, gg, pt):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion", "c1", "c3"])
+    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion", "c1", "c3", "c5"])
     ap.add_argument("--workload", default=None)
     ap.add_argument("--limit-ms", type=int, default=600000)
     ap.add_argument("--tune-budget", type=float, default=60.0)
@@ -196,6 +242,9 @@ def main(argv=None):
     elif args.what == "c3":
         args.workload = args.workload or "rmat20_16m"
         c3(args, pg, gg, pt)
+    elif args.what == "c5":
+        args.workload = args.workload or "rmat22_64m"
+        c5(args, pg, gg, pt)
     else:
         small(args, pg, gg, pt)
     return 0

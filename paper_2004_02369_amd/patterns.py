@@ -89,6 +89,18 @@ def extend_by_edge(patterns: list[dict]) -> list[dict]:
 
 
 # Named patterns of the paper's evaluation whose shapes the text states.
-P7_TRIANGLE_NO_K4 = {"k": 3, "edges": [(0, 1), (1, 2), (0, 2)], "av": [[0, 1, 2]]}   # Sec. 6.2, p7
+P7_TRIANGLE_NO_K4 = {"k": 3, "edges": [(0, 1), (1, 2), (0, 2)], "av": [[0, 1, 2]]}   # Sec. 6.5, p7
 P8_INDUCED_DIAMOND = {"k": 4, "edges": [(0, 1), (1, 2), (2, 3), (3, 0), (1, 3)], "induced": True}  # p8
 PA_TWO_COMMON_FRIENDS = {"k": 4, "edges": [(0, 1), (1, 2), (2, 3), (3, 0)], "anti": [(1, 3)]}  # Sec. 3.1.1 p_a
+
+# 5-vertex patterns whose every edge touches the edge (0, 1): their core is
+# that one edge, and the other three vertices are completed from set sizes
+# (the edge's common neighbours and each end's own neighbours).
+EDGE_CORE_5 = {
+    # triangle 0-1-2 with two pendant vertices on vertex 0
+    "cricket": {"k": 5, "edges": [(0, 1), (0, 2), (1, 2), (0, 3), (0, 4)]},
+    # triangle 0-1-2 with one pendant on vertex 0 and one on vertex 1
+    "bull": {"k": 5, "edges": [(0, 1), (0, 2), (1, 2), (0, 3), (1, 4)]},
+    # three triangles sharing the edge 0-1 (the book K_{1,1,3})
+    "book3": {"k": 5, "edges": [(0, 1), (0, 2), (1, 2), (0, 3), (1, 3), (0, 4), (1, 4)]},
+}

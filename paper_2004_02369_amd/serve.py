@@ -89,6 +89,7 @@ class Query:
     name: str
     kind: str
     plans: list
+    specs: list = field(default_factory=list)
 
     def __post_init__(self):
         if self.kind not in ("count", "exists"):
@@ -414,9 +415,12 @@ class Server:
 
 # -------------------------------------------------------------- workloads
 
-def catalogue(pg, pt):
-    """The query catalogue: (name, kind, pattern specs)."""
-    ent = [("triangle", "count", [pt.clique(3)]), ("wedge", "count", [pt.star(3)])]
+def catalogue_specs(pt):
+    """The query catalogue as plain specs: (name, kind, pattern specs).
+    Counts of 3-5 vertices, k-clique existence with early exit (Sec. 3.2.2),
+    and patterns with anti-edges (Sec. 3.1.1)."""
+    ent = [("triangle", "count", [pt.clique(3)]), ("wedge", "count", [pt.star(3)]),
+           ("induced_wedge", "count", [pt.star(3, induced=True)])]
     for i, s in enumerate(pt.all_vertex_induced(4)):
         ent.append((f"induced4_{i}", "count", [s]))
     ent += [("clique4", "count", [pt.clique(4)]), ("clique5", "count", [pt.clique(5)])]
@@ -425,8 +429,16 @@ def catalogue(pg, pt):
             ("two_common_friends", "count", [pt.PA_TWO_COMMON_FRIENDS])]
     trees5 = [s for s in pt.all_edge_induced(4) if s["k"] == 5]
     ent += [(f"tree5_{i}", "count", [s]) for i, s in enumerate(trees5)]
-    # one plan per typed pattern: entries that ask the same question (K4
-    # and the induced K4) share a plan, so their requests merge in a launch
+    # 5-vertex patterns whose core is one edge: every other vertex is
+    # counted from the sizes of that edge's rows
+    ent += [(name, "count", [spec]) for name, spec in pt.EDGE_CORE_5.items()]
+    return ent
+
+
+def catalogue(pg, pt):
+    """The query catalogue: (name, kind, plans), one plan per typed pattern:
+    entries that ask the same question (K4 and the induced K4) share a plan,
+    so their requests merge in a launch."""
     plans = {}
 
     def plan(spec):
@@ -434,7 +446,7 @@ def catalogue(pg, pt):
         if key not in plans:
             plans[key] = pg.plan_pattern(spec)
         return plans[key]
-    return [Query(name, kind, [plan(s) for s in specs]) for name, kind, specs in ent]
+    return [Query(name, kind, [plan(s) for s in specs], list(specs)) for name, kind, specs in catalogue_specs(pt)]
 
 
 def pattern_key(spec) -> str:

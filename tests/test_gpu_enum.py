@@ -101,8 +101,8 @@ def test_window_errors(pg, g_small):
 
 def test_enumerate_at_workload_size(pg, orc):
     """K4 and triangles of the six-motif Chung-Lu workload into one device
-    buffer: every row valid and distinct by a sampled check, totals equal
-    to the oracle's counts."""
+    buffer: every row valid, no two rows on one vertex set, totals equal to
+    the oracle's counts."""
     import json
     import os
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "expected.json")) as f:
@@ -117,18 +117,19 @@ def test_enumerate_at_workload_size(pg, orc):
         perm = G.perm
         inv = np.empty_like(perm)
         inv[perm] = np.arange(len(perm), dtype=perm.dtype)
-        rng = np.random.default_rng(7)
-        sample = rows[rng.integers(0, len(rows), 20000)]
-        # sampled rows: distinct vertices, all pairs adjacent in the CSR
+        # every row: distinct vertices, every pattern edge an edge of the
+        # graph (looked up in the sorted edge keys), and no two rows on the
+        # same vertex set (a clique has one match per set)
         rp, col = G.csr()
-        r = inv[sample]
+        r = inv[rows].astype(np.int64)
+        n = np.int64(G.n)
+        ekeys = np.repeat(np.arange(G.n, dtype=np.int64), np.diff(rp)) * n + col.astype(np.int64)
         for a in range(spec["k"]):
             for b in range(a + 1, spec["k"]):
-                u, v = r[:, a], r[:, b]
-                pos = np.array([np.searchsorted(col[rp[x]:rp[x + 1]], y) for x, y in zip(u, v)])
-                ok = np.array([p < rp[x + 1] - rp[x] and col[rp[x] + p] == y for p, x, y in zip(pos, u, v)])
-                assert ok.all()
-        if spec["k"] == 3:
-            canon = np.sort(rows.astype(np.int64), axis=1)
-            key = (canon[:, 0] << 40) | (canon[:, 1] << 20) | canon[:, 2]
-            assert len(np.unique(key)) == len(key)
+                key = r[:, a] * n + r[:, b]
+                pos = np.minimum(np.searchsorted(ekeys, key), len(ekeys) - 1)
+                assert np.all(ekeys[pos] == key), (a, b)
+        canon = np.sort(r, axis=1)
+        order = np.lexsort(canon.T[::-1])
+        canon = canon[order]
+        assert np.all(np.any(canon[1:] != canon[:-1], axis=1))

@@ -151,6 +151,18 @@ def test_hub_star_graph(pg):
     assert pg.count(S, pg.plan_pattern(pt.star(5))) == math.comb(4000, 4)
 
 
+def test_choose_near_two_to_the_64(pg):
+    """C(d, 4) for a 120,000-leaf star is about 8.6e18: exact in 64 bits
+    although 4 * C(d, 4) is not, so the count must come back, not an
+    overflow."""
+    say("star(5) on a 120,000-leaf star")
+    S = G(pg, gg.star(120000))
+    want = math.comb(120000, 4)
+    assert 2 ** 62 <= want < 2 ** 64
+    assert pg.count(S, pg.plan_pattern(pt.star(5))) == want
+    assert pg.count(S, pg.plan_pattern(pt.star(5, induced=True))) == want
+
+
 def test_overflow_reported(pg):
     say("overflow")
     S = G(pg, gg.star(3000))
@@ -191,6 +203,20 @@ def test_batched_equals_single_and_perturbations(pg, orc):
         assert pg.count(Gd, plans, grid_waves=grid, chunk=chunk, flags=flags) == batched
 
 
+def test_merge_model_bytes_deterministic(pg):
+    """Claims cover fixed task ranges, so the merge-model byte count of a
+    launch is the same for every run and every grid size."""
+    g = gg.chung_lu(3000, 24000, 2.1, 300.0, seed=21)
+    say("merge-model bytes across grids")
+    Gd = G(pg, g)
+    plans = [pg.plan_pattern(s) for s in pt.all_vertex_induced(4)]
+    seen = set()
+    for grid in (64, 256, 1024, 0, 0):
+        c, st = pg.count_ex(Gd, plans, grid_waves=grid, flags=pg.PG_RUN_COUNT_BYTES)
+        seen.add(st["logical_bytes"])
+    assert len(seen) == 1 and seen.pop() > 0
+
+
 def test_relabelling_invariance(pg):
     g = gg.chung_lu(2500, 15000, 2.1, 250.0, seed=5)
     specs = pt.all_vertex_induced(4)
@@ -214,11 +240,22 @@ def test_clique_existence(pg):
 
 
 def _orbit_keys(rows, spec):
-    k = spec["k"]
-    E = {frozenset(e) for e in spec["edges"]}
-    auts = [p for p in itertools.permutations(range(k))
-            if all((frozenset((p[a], p[b])) in E) == (frozenset((a, b)) in E)
-                   for a, b in itertools.combinations(range(k), 2))]
+    """One key per orbit of matches under the typed automorphisms (permutations
+    keeping true edges, anti-edges, anti-vertex neighbourhoods and labels)."""
+    k, E, A, av, labels, avl = brute._pattern_sets(spec)
+    av_items = sorted((tuple(sorted(a)), l) for a, l in zip(av, avl))
+    auts = []
+    for p in itertools.permutations(range(k)):
+        if any(labels[i] != labels[p[i]] for i in range(k)):
+            continue
+        if not all(((frozenset((p[a], p[b])) in E) == (frozenset((a, b)) in E)) and
+                   ((frozenset((p[a], p[b])) in A) == (frozenset((a, b)) in A))
+                   for a, b in itertools.combinations(range(k), 2)):
+            continue
+        if sorted((tuple(sorted(p[x] for x in a)), l) for a, l in zip(av, avl)) != av_items:
+            continue
+        auts.append(p)
+    assert len(auts) == brute.typed_aut(spec)
     return {min(tuple(r[p[i]] for i in range(k)) for p in auts) for r in rows}
 
 
@@ -228,7 +265,8 @@ def test_enumerate_matches_orbits(pg, orc):
     Gd = G(pg, g)
     adj = brute._adj_sets(*g)
     for spec in (pt.clique(3), pt.star(4), DIAMOND, pt.chain(4), pt.clique(4), {"k": 4, "edges": [(0, 1), (1, 2), (2, 0), (0, 3)]},
-                 pt.P8_INDUCED_DIAMOND, pt.PA_TWO_COMMON_FRIENDS):
+                 pt.P8_INDUCED_DIAMOND, pt.PA_TWO_COMMON_FRIENDS, pt.star(4, induced=True), pt.chain(4, induced=True),
+                 pt.P7_TRIANGLE_NO_K4, {"k": 4, "edges": [(0, 1), (1, 2), (2, 3), (3, 0)], "anti": [(0, 2)]}):
         plan = pg.plan_pattern(spec)
         rows, total = pg.enumerate_matches(Gd, plan)
         want = orc.count(orc.Graph.from_tuple(g), spec)
@@ -236,8 +274,8 @@ def test_enumerate_matches_orbits(pg, orc):
         for r in rows:
             assert brute.is_valid_map(adj, None, spec, tuple(int(x) for x in r))
         assert len({tuple(r) for r in rows.tolist()}) == len(rows)
-        if not spec.get("anti") and not spec.get("induced"):
-            assert len(_orbit_keys(rows.tolist(), spec)) == len(rows)
+        # one row per orbit of the typed pattern's automorphisms
+        assert len(_orbit_keys(rows.tolist(), spec)) == len(rows), spec
 
 
 def test_enumerate_capacity(pg):

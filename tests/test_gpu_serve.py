@@ -204,3 +204,40 @@ def test_serving_alone_equals_in_mix(pg, g_mid):
     summ = serve.summarize(reqs, t0)
     say(f"mix: p50 {summ['p50_ms']:.2f} ms, p99 {summ['p99_ms']:.2f} ms, "
         f"{summ['completed_qps']:.0f} QPS, {srv.launches} launches ({len(wide)} wide)")
+
+
+def test_served_results_equal_oracle(pg, orc):
+    """Every catalogue query, served alone and in a Poisson mix, gives the
+    oracle's answer (counts by valid maps / |Aut_t|, closed forms and the
+    existence search, written by tests/golden/make_golden.py)."""
+    with open(os.path.join(HERE, "golden", "expected.json")) as f:
+        w = json.load(f)["workloads"]["serve_cl5k"]
+    gold = {serve.pattern_key(a["spec"]): a["answer"] for a in w["answers"]}
+    prm = w["params"]
+    say("served results vs oracle on chung_lu 5000/25000")
+    G = pg.load_graph(*gg.chung_lu(prm["n"], prm["m"], prm["gamma"], prm["w_max"], seed=prm["seed"]), device=0)
+    assert G.m == w["m"]
+    queries = serve.catalogue(pg, pt)
+    want = {}
+    for q in queries:
+        assert len(q.specs) == 1
+        key = serve.pattern_key(q.specs[0])
+        assert key in gold, f"no oracle answer for {q.name}"
+        want[q.name] = gold[key] if q.kind == "exists" else [gold[key]]
+    assert any(v is True for v in want.values()) and any(v is False for v in want.values())
+    probe = serve.Server(G, 1 << 20, slots=3)
+    biggest = max(probe.size_of(q.plans, q.kind) for q in queries)
+    alone = serve.standalone(G, queries, biggest, limit_ms=60000)
+    for q in queries:
+        res, _, err = alone[q.name]
+        assert err is None, (q.name, err)
+        assert res == want[q.name], (q.name, res, want[q.name])
+    srv = serve.Server(G, 2 * biggest + 4096, slots=3, time_limit_ms=120000,
+                       policy=serve.policy_from(queries, alone, 3, light_ms=5.0))
+    times, picks = serve.poisson_arrivals(2000.0, 400, len(queries), seed=12)
+    reqs, t0 = serve.run_open_loop(srv, queries, times, picks)
+    assert len(reqs) == 400 and srv.idle()
+    for r in reqs:
+        assert r.error is None, (r.query.name, r.error)
+        assert r.result == want[r.query.name], r.query.name
+    assert srv.merged_requests > 0

@@ -112,3 +112,59 @@ def test_inversion_route_equals_induced_route(pg, orc):
     got5 = motifs.induced_counts(G5, 5, pg)
     want5 = [w5["induced5"][str(orc.canonical_of_edges(5, list(s)))]["count"] for s in motifs.shapes(5)]
     assert got5 == want5
+
+
+def test_hub_row_longer_than_the_arena(pg, orc):
+    """A hub of degree 40,000 (longer than a wavefront's 32,768-int arena):
+    level-2 sets driven by its row take the one-parent route.  Triangles,
+    wedges and the six induced 4-motifs against the oracle's closed forms,
+    with the default knobs and with flattened batches forced."""
+    w = GOLD["hub40k"]
+    say("hub40k: hub of degree 40,000 + G(40000, 120000) among its leaves")
+    G = pg.load_graph(*gg.hub_plus_er(**w["params"]), device=0)
+    assert G.m == w["m"] and G.d_max == w["d_max"] == 40000
+    specs = pt.all_vertex_induced(4)
+    plans = [pg.plan_pattern(s) for s in specs]
+    want = _motif_expect(orc, w["induced4"], 4, specs)
+    for knobs in ({}, {"batch_max_avg": 0}, {"batch_max_avg": 16}, {"flags": pg.PG_RUN_NO_TASK_BATCH}):
+        say(f"hub40k six motifs, knobs {knobs}")
+        assert pg.count(G, plans, **knobs) == want, knobs
+    assert pg.count(G, [pg.plan_pattern(pt.clique(3)), pg.plan_pattern(pt.star(3)),
+                        pg.plan_pattern(pt.star(4))]) == [w["triangle"], w["sum_c_d_2"], w["sum_c_d_3"]]
+
+
+def _five_rows_check(orc, specs, got, w):
+    """The 21 induced 5-motif counts satisfy every closed-form row
+    N(P) = sum_Q c(P, Q) I(Q) the oracle wrote (Sec. 3.1.3 relates edge-
+    and vertex-induced matches); the 4-star row is sum_v C(d_v, 4)."""
+    census = {orc.canonical_of_edges(5, s["edges"]): c for s, c in zip(specs, got)}
+    rows = orc.noninduced5_rows(census)
+    assert rows == w["noninduced5"]
+    assert rows["star4"] == w["sum_c_d_4"]
+
+
+def test_rmat10_22_plans(pg, orc):
+    w = GOLD["rmat10_4k"]
+    say("rmat10_4k 21 induced 5-motifs + K5 batched")
+    G = pg.load_graph(*gg.rmat(**w["params"]), device=0)
+    assert G.m == w["m"]
+    specs = pt.all_vertex_induced(5) + [pt.clique(5)]
+    plans = [pg.plan_pattern(s) for s in specs]
+    got = pg.count(G, plans)
+    want = _motif_expect(orc, w["induced5"], 5, specs[:-1]) + [w["clique5"]]
+    assert got == want
+    _five_rows_check(orc, specs[:-1], got[:-1], w)
+
+
+def test_rmat12_22_plans_closed_form_rows(pg, orc):
+    """R-MAT scale 12 (65,536 edges): the 5-motif census is beyond the
+    oracle, so the 21 GPU counts are checked against five closed-form rows
+    and K5 against the induced K5."""
+    w = GOLD["rmat12_64k"]
+    say("rmat12_64k 21 induced 5-motifs + K5 batched (about 20 s)")
+    G = pg.load_graph(*gg.workload("rmat12_64k"), device=0)
+    assert G.m == w["m"]
+    specs = pt.all_vertex_induced(5) + [pt.clique(5)]
+    got = pg.count(G, [pg.plan_pattern(s) for s in specs])
+    assert got[-1] == got[-2]
+    _five_rows_check(orc, specs[:-1], got[:-1], w)

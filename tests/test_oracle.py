@@ -263,8 +263,63 @@ def test_p8_induced_diamond(orc):
     assert orc.count(G(orc, (n, u[keep], v[keep])), P8) == 1
 
 
-def test_prgu_relation(orc):
-    """Counting all valid maps (no symmetry breaking) gives count x |Aut|."""
-    og = G(orc, gg.erdos_renyi_m(60, 400, seed=3))
-    for spec in (CLIQUE(3), STAR(4), DIAMOND, PAW, P8):
-        assert orc.valid_maps(og, spec) == orc.count(og, spec) * orc.aut(spec)
+def test_valid_maps_brute_force(orc):
+    """The oracle's valid-map count (no symmetry breaking) equals the number of
+    injective maps that satisfy every match condition, listed exhaustively
+    (Sec. 2.1 and Sec. 3.1), on tiny graphs with and without anti-edges and
+    anti-vertices."""
+    for seed in (3, 4, 5):
+        g = gg.gnp(9, 0.5, seed=seed)
+        og = G(orc, g)
+        for spec in (CLIQUE(3), STAR(4), DIAMOND, PAW, P8, PA, P7, PD, PE):
+            assert orc.valid_maps(og, spec) == len(brute.canonical_maps(g, spec)), (seed, spec)
+
+
+def test_valid_maps_from_partition_and_brute_force(orc):
+    """valid_maps_from counts the valid maps whose pattern vertex 0 lands in
+    the given roots: over a partition of V it sums to valid_maps, and on a
+    tiny graph it equals the brute-force maps with img[0] in the roots."""
+    g = gg.chung_lu(300, 1500, 2.1, 40.0, seed=17)
+    og = G(orc, g)
+    rng = np.random.Generator(np.random.PCG64(5))
+    parts = np.array_split(rng.permutation(og.n).astype(np.int32), 7)
+    for spec in (CLIQUE(3), PATH(4), P8, P7):
+        total = orc.valid_maps(og, spec)
+        assert sum(orc.valid_maps_from(og, spec, p) for p in parts) == total, spec
+        assert orc.valid_maps_from(og, spec, np.zeros(0, np.int32)) == 0
+    t = gg.gnp(9, 0.55, seed=8)
+    ot = G(orc, t)
+    for spec in (CLIQUE(3), STAR(4), P8, PD):
+        maps = brute.canonical_maps(t, spec)
+        for roots in ([0], [1, 4, 7], list(range(9))):
+            want = sum(1 for m in maps if m[0] in roots)
+            assert orc.valid_maps_from(ot, spec, np.array(roots, np.int32)) == want, (spec, roots)
+
+def test_noninduced5_closed_forms(orc):
+    """Each 5-vertex closed form equals the generic matcher's count of the
+    same (edge-induced) pattern, and the row sum_Q c(P, Q) I(Q) of the ESU
+    census, on graphs with hubs, triangles and isolated vertices."""
+    graphs = [gg.gnp(11, 0.45, seed=s) for s in (1, 2)] + [
+        gg.chung_lu(250, 1200, 2.1, 40.0, seed=23), gg.complete(7),
+        gg.disjoint_union(gg.star(9), gg.complete(5), gg.cycle(6))]
+    for g in graphs:
+        og = G(orc, g)
+        cf = orc.noninduced5_closed_forms(og)
+        census = orc.motif_census(og, 5)
+        rows = orc.noninduced5_rows(census)
+        for name, edges in orc.FIVE_NONINDUCED.items():
+            direct = orc.count(og, {"k": 5, "edges": edges})
+            assert cf[name] == direct == rows[name], (name, cf[name], direct, rows[name])
+
+
+def test_exists_equals_count_positive(orc):
+    """Existence (a search stopped at the first valid map) is count > 0:
+    cliques in complete multipartite graphs (K_k exists iff k <= parts),
+    and patterns with anti-edges and anti-vertices on random graphs."""
+    for parts, k in (([2] * 6, 6), ([2] * 6, 7), ([3] * 4, 4), ([3] * 4, 5)):
+        og = G(orc, gg.complete_multipartite(parts))
+        assert orc.exists(og, CLIQUE(k)) is (k <= len(parts))
+    for seed in (1, 2, 3):
+        og = G(orc, gg.gnp(12, 0.3, seed=seed))
+        for spec in (CLIQUE(3), CLIQUE(4), P7, P8, PA, PD, STAR(5)):
+            assert orc.exists(og, spec) is (orc.count(og, spec) > 0), (seed, spec)
