@@ -9,6 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpg.so")
+ROWBENCH = os.path.join(HERE, "librowbench.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["api.cpp", "plan.cpp", "engine.hip"]
@@ -49,6 +50,10 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     _run([HIPCC, *DEVICE, "-shared", "-fPIC", *objs, "-o", tmp])
     os.replace(tmp, LIB)
+    # the measurement kernels (streaming reads, row-pair intersections)
+    tmp = ROWBENCH + ".tmp%d" % os.getpid()
+    _run([HIPCC, *COMMON, *DEVICE, "-x", "hip", "-shared", os.path.join(CSRC, "rowbench.hip"), "-o", tmp])
+    os.replace(tmp, ROWBENCH)
     return LIB
 
 

@@ -476,13 +476,13 @@ struct Ctx {
             const int npos = (N.base >= 0 ? 1 : 0) + __builtin_popcount(N.t_isect);
             const int ndiff = __builtin_popcount(N.t_diff);
             bool complement = false;
-            // labelled plans: a label part as the positive operand already
-            // holds only candidates with the label, and with no difference
-            // rows the count is |P| less the excluded images in it
+            // with one positive operand and no difference rows the count is
+            // |P| less the excluded images in it (no walk); in labelled plans
+            // a label part as that operand already holds only candidates
+            // with the label
             const bool lab_part = kFac && N.label >= 0 && P.lab_off && drv != kBaseOp;
-            if (!emit && npos == 1 && (N.label < 0 || lab_part) && N.av_count == 0 &&
-                (ndiff >= 1 || (kFac && ndiff == 0)) && ndiff <= kMaxDiffB && !(P.run_flags & PG_RUN_NO_MODE_B) &&
-                dlen > 0) {
+            if (!emit && npos == 1 && (N.label < 0 || lab_part) && N.av_count == 0 && ndiff <= kMaxDiffB &&
+                !(P.run_flags & PG_RUN_NO_MODE_B) && dlen > 0) {
                 // restricted difference rows become the complement's segments
                 int k = 0;
                 for (uint32_t s = N.t_diff; s; s &= s - 1, k++) {
@@ -528,9 +528,12 @@ struct Ctx {
                 }
                 // direct: every element of P is probed against each D; by
                 // complement: an element of D_k against P and D_0..D_k-1
-                complement = (kFac && ndiff == 0) || (long long)sl0 + 2ll * sl1 + 3ll * sl2 < (long long)ndiff * dlen;
+                complement = ndiff == 0 || (long long)sl0 + 2ll * sl1 + 3ll * sl2 < (long long)ndiff * dlen;
             }
             if (P.run_flags & PG_RUN_COUNT_BYTES) {
+                // a count taken from a length (one operand, no difference
+                // rows) executes no set operation: it moves no merge bytes
+                if (complement && ndiff == 0) bytes = 0;
                 for (uint32_t s = N.t_diff; s; s &= s - 1) {
                     int32_t n;
                     restrict_row(row(__builtin_ctz(s), l), lo, hi, &n);

@@ -10,6 +10,8 @@
                                                      # each alone under a time limit, the finishing ones batched
     python -m paper_2004_02369_amd.measure c5        # the serving catalogue's count queries on R-MAT scale 22
                                                      # (64M edges): each alone (time, merge-model bytes), then batched
+    python -m paper_2004_02369_amd.measure rows      # achievable HBM read bandwidth, and row-pair intersections
+                                                     # on the R-MAT scale 22 rows by variant and row length
 """
 from __future__ import annotations
 
@@ -196,6 +198,61 @@ def c5(args, pg, gg, pt):
     print(json.dumps(out), flush=True)
 
 
+def rows(args, pg, gg, pt):
+    """Achievable HBM read bandwidth (a 4 GiB streaming read), then
+    |N(u) & N(v)| over row pairs of random edges of the serving graph, by
+    intersection variant and by length bucket, with the caches flushed
+    before every launch.  Work per pair is the merge model's 4 (|A| + |B|)
+    bytes; all variants must return the same counts."""
+    import numpy as np
+    import torch
+    from . import rowbench as rb
+    dev = torch.device("cuda:0")
+    buf = torch.ones(1 << 30, dtype=torch.int32, device=dev)  # 4 GiB
+    ms, _ = rb.stream_read(buf, reps=5)
+    peak = 4.0 * buf.numel() / (ms * 1e-3) / 1e9
+    out = {"measure": "rows", "workload": args.workload, "stream_read_gb_per_s": peak,
+           "stream_read_bytes": 4 * buf.numel()}
+    _say(f"streaming read: {peak:.0f} GB/s")
+    flush_buf = buf[: 1 << 28]  # 1 GiB, larger than L2 and the last-level cache
+    G = pg.load_graph(*gg.workload(args.workload), device=0)
+    rp_h, col_h = G.csr()
+    rp = torch.from_numpy(rp_h).to(dev)
+    col = torch.from_numpy(col_h).to(dev)
+    rng = np.random.Generator(np.random.PCG64(args.seed))
+    slots = rng.integers(0, len(col_h), args.pairs)
+    u = (np.searchsorted(rp_h, slots, side="right") - 1).astype(np.int32)
+    v = col_h[slots].astype(np.int32)
+    deg = np.diff(rp_h)
+    size = deg[u] + deg[v]
+    edges = [0, 64, 512, 4096, 32768, 1 << 40]
+    out["buckets"] = []
+    for lo, hi in zip(edges[:-1], edges[1:]):
+        sel = np.nonzero((size >= lo) & (size < hi))[0]
+        if len(sel) == 0:
+            continue
+        pu = torch.from_numpy(u[sel]).to(dev)
+        pv = torch.from_numpy(v[sel]).to(dev)
+        nbytes = 4 * int(size[sel].sum())
+        rec = {"len_lo": lo, "len_hi": hi if hi < (1 << 40) else None, "pairs": len(sel), "merge_bytes": nbytes}
+        ref = None
+        for name, var in rb.VARIANTS.items():
+            o = torch.zeros(len(sel), dtype=torch.int32, device=dev)
+            best = float("inf")
+            for _ in range(3):
+                rb.flush(flush_buf)
+                best = min(best, rb.intersect(var, rp, col, pu, pv, o))
+            got = o.cpu().numpy()
+            if ref is None:
+                ref = got
+            assert np.array_equal(got, ref), f"variant {name} differs"
+            rec[name] = {"ms": best, "gb_per_s": nbytes / (best * 1e-3) / 1e9,
+                         "frac_of_stream": nbytes / (best * 1e-3) / 1e9 / peak}
+        _say(f"[{lo}, {hi}): {len(sel)} pairs " + ", ".join(f"{k} {rec[k]['gb_per_s']:.0f} GB/s" for k in rb.VARIANTS))
+        out["buckets"].append(rec)
+    print(json.dumps(out), flush=True)
+
+
 def small(args, pg, gg, pt):
     """Launch-bound regime: the six induced 4-motifs on ER 2k/20k, one
     batched launch against six launches, best of several repetitions."""
@@ -219,7 +276,9 @@ def small(args, pg, gg, pt):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion", "c1", "c3", "c5"])
+    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion", "c1", "c3", "c5", "rows"])
+    ap.add_argument("--pairs", type=int, default=2_000_000)
+    ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--workload", default=None)
     ap.add_argument("--limit-ms", type=int, default=600000)
     ap.add_argument("--tune-budget", type=float, default=60.0)
@@ -242,6 +301,9 @@ def main(argv=None):
     elif args.what == "c3":
         args.workload = args.workload or "rmat20_16m"
         c3(args, pg, gg, pt)
+    elif args.what == "rows":
+        args.workload = args.workload or "rmat22_64m"
+        rows(args, pg, gg, pt)
     elif args.what == "c5":
         args.workload = args.workload or "rmat22_64m"
         c5(args, pg, gg, pt)

@@ -206,13 +206,36 @@ def test_serving_alone_equals_in_mix(pg, g_mid):
         f"{summ['completed_qps']:.0f} QPS, {srv.launches} launches ({len(wide)} wide)")
 
 
+def _iso_key(spec):
+    """The typed pattern up to relabelling: the smallest (true edges,
+    anti-edges) listing over all orders of the vertices (an induced spec's
+    implied anti-edges included)."""
+    import itertools
+    k = spec["k"]
+    E = {tuple(sorted(e)) for e in spec["edges"]}
+    A = {tuple(sorted(e)) for e in spec.get("anti") or []}
+    if spec.get("induced"):
+        A |= {(a, b) for a, b in itertools.combinations(range(k), 2) if (a, b) not in E}
+    assert not spec.get("av") and not spec.get("labels")
+    if len(E) == k * (k - 1) // 2:  # a clique is its own canonical form
+        return (k, tuple(sorted(E)), ())
+    assert k <= 6
+    best = None
+    for p in itertools.permutations(range(k)):
+        key = (tuple(sorted(tuple(sorted((p[a], p[b]))) for a, b in E)),
+               tuple(sorted(tuple(sorted((p[a], p[b]))) for a, b in A)))
+        if best is None or key < best:
+            best = key
+    return (k,) + best
+
+
 def test_served_results_equal_oracle(pg, orc):
     """Every catalogue query, served alone and in a Poisson mix, gives the
     oracle's answer (counts by valid maps / |Aut_t|, closed forms and the
     existence search, written by tests/golden/make_golden.py)."""
     with open(os.path.join(HERE, "golden", "expected.json")) as f:
         w = json.load(f)["workloads"]["serve_cl5k"]
-    gold = {serve.pattern_key(a["spec"]): a["answer"] for a in w["answers"]}
+    gold = {_iso_key(a["spec"]): a["answer"] for a in w["answers"]}
     prm = w["params"]
     say("served results vs oracle on chung_lu 5000/25000")
     G = pg.load_graph(*gg.chung_lu(prm["n"], prm["m"], prm["gamma"], prm["w_max"], seed=prm["seed"]), device=0)
@@ -221,18 +244,20 @@ def test_served_results_equal_oracle(pg, orc):
     want = {}
     for q in queries:
         assert len(q.specs) == 1
-        key = serve.pattern_key(q.specs[0])
+        key = _iso_key(q.specs[0])
         assert key in gold, f"no oracle answer for {q.name}"
         want[q.name] = gold[key] if q.kind == "exists" else [gold[key]]
     assert any(v is True for v in want.values()) and any(v is False for v in want.values())
-    probe = serve.Server(G, 1 << 20, slots=3)
-    biggest = max(probe.size_of(q.plans, q.kind) for q in queries)
-    alone = serve.standalone(G, queries, biggest, limit_ms=60000)
+    def biggest(slots):
+        probe = serve.Server(G, 1 << 20, slots=slots)
+        return max(probe.size_of(q.plans, q.kind) for q in queries)
+
+    alone = serve.standalone(G, queries, biggest(1), limit_ms=60000)
     for q in queries:
         res, _, err = alone[q.name]
         assert err is None, (q.name, err)
         assert res == want[q.name], (q.name, res, want[q.name])
-    srv = serve.Server(G, 2 * biggest + 4096, slots=3, time_limit_ms=120000,
+    srv = serve.Server(G, 2 * biggest(3) + 4096, slots=3, time_limit_ms=120000,
                        policy=serve.policy_from(queries, alone, 3, light_ms=5.0))
     times, picks = serve.poisson_arrivals(2000.0, 400, len(queries), seed=12)
     reqs, t0 = serve.run_open_loop(srv, queries, times, picks)

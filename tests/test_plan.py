@@ -26,13 +26,13 @@ def built():
         build.build()
 
 
-def header_functions():
+def header_functions(prefix="pg_", header=None):
     names = set()
     for fn in os.listdir(os.path.join(ROOT, "include")):
-        if fn.endswith(".h"):
+        if fn.endswith(".h") and (header is None or fn == header):
             txt = open(os.path.join(ROOT, "include", fn)).read()
             txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-            names |= set(re.findall(r"^\s*(?:const\s+)?[\w]+\s*\**\s*(pg_\w+)\s*\(", txt, flags=re.M))
+            names |= set(re.findall(r"^\s*(?:const\s+)?[\w]+\s*\**\s*(" + prefix + r"\w+)\s*\(", txt, flags=re.M))
     return names
 
 
@@ -43,6 +43,15 @@ def test_abi_exports_every_declared_symbol():
     for n in sorted(names):
         assert hasattr(L, n), n
     assert set(pg.EXPORTS) == names
+
+
+def test_rowbench_exports_every_declared_symbol():
+    from paper_2004_02369_amd import rowbench
+    names = header_functions("rb_", "rowbench.h")
+    assert {"rb_stream_read", "rb_flush", "rb_intersect", "rb_last_error"} == names == set(rowbench.EXPORTS)
+    L = rowbench.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
 
 
 # ------------------------------------------------------------ worked example
