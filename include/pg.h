@@ -86,6 +86,9 @@ typedef struct {
 pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t *dst,
                         const int16_t *labels, const pg_options *opt, pg_graph **out);
 
+/* Sizes of the resident graph and its degree order (Sec. 5.2: vertices are
+ * ranked by degree; perm maps a rank back to the caller's id), plus the
+ * launch residency the engine sizes its grids from.  out: host. */
 pg_status pg_graph_info(const pg_graph *g, pg_graph_info_t *out);
 
 /* Copy the resident CSR back to the host in rank ids: row_ptr n+1 entries,
@@ -238,7 +241,9 @@ pg_status pg_count_ex(pg_graph *g, const pg_plan *const *plans, int32_t n_plans,
 pg_status pg_exists(pg_graph *g, const pg_plan *plan, int32_t *found, void *hip_stream);
 
 /* Enumerate every match once (one canonical representative per set of
- * automorphic matches).  out: device memory of cap * k int32, row i holds
+ * automorphic matches): match(G, p, f) of Sec. 3.2 (Fig. "program
+ * examples") with the matches written to device memory instead of passed
+ * to a callback.  out: device memory of cap * k int32, row i holds
  * match i as original vertex ids indexed by pattern vertex.  n_total
  * receives the number of matches even when it exceeds cap (then only the
  * first cap rows, in unspecified order, are written). */
