@@ -236,6 +236,22 @@ pg_status pg_count(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, ui
 pg_status pg_count_ex(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts,
                       const pg_run_config *cfg, pg_run_stats *stats, void *hip_stream);
 
+/* pg_count_ex for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops and harnesses that must not call
+ * hipMalloc): the control block, the program trie and the per-wavefront
+ * scratch come from one fixed device array of 256 MiB that the library
+ * holds on every device it runs on until the process ends.  Makes no
+ * device allocation.  The grid (cfg->grid_waves, or the default) is
+ * reduced to the wavefronts whose scratch fits the array; PG_ENOMEM with a
+ * message when not even one wavefront's scratch fits (enumeration levels x
+ * the largest degree, plus a 128 KB arena) or the trie does not.  Every
+ * call on one device shares that array and leaves its contents behind:
+ * calls that overlap on one device race, so callers serialise them (one
+ * stream, or their own lock).  counts: host, n_plans entries.  Synchronous
+ * on hip_stream; no run statistics. */
+pg_status pg_count_noalloc(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts,
+                           const pg_run_config *cfg, void *hip_stream);
+
 /* Existence query with early termination (Sec. 3.2.2, Sec. 5.3): found = 1
  * if the pattern has at least one match.  Returns PG_OK either way. */
 pg_status pg_exists(pg_graph *g, const pg_plan *plan, int32_t *found, void *hip_stream);

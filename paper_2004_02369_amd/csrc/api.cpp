@@ -842,6 +842,59 @@ pg_status pg_count_ex(pg_graph *g, const pg_plan *const *plans, int32_t n_plans,
     }
 }
 
+pg_status pg_count_noalloc(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts,
+                           const pg_run_config *cfg, void *hip_stream) {
+    if (!counts) { set_error("counts is NULL"); return PG_EINVAL; }
+    try {
+        pg_status st = check_args(g, plans, n_plans, cfg);
+        if (st) return st;
+        DeviceGuard guard(g->device);
+        hipStream_t s = reinterpret_cast<hipStream_t>(hip_stream);
+        LaunchPlan L;
+        std::vector<const pg::PlanImpl *> impls;
+        for (int i = 0; i < n_plans; i++) impls.push_back(&plans[i]->impl);
+        L.trie = pg::build_trie(impls, false);
+        if ((st = check_trie(L.trie))) return st;
+        shape(g, cfg, L, pg::kModeCount, false);
+        void *base = nullptr;
+        size_t cap = 0;
+        PG_HIP(pg::static_scratch(&base, &cap));
+        // [control block | trie | scratch of as many wavefronts as fit]
+        const size_t ctl_b = align_up(kCtlWords * sizeof(unsigned long long)), trie_b = align_up(L.image.size());
+        if (ctl_b + trie_b > cap) {
+            set_error("the program trie (" + std::to_string(L.image.size()) + " bytes) does not fit the fixed " +
+                      std::to_string(cap >> 20) + " MiB device array");
+            return PG_ENOMEM;
+        }
+        const size_t per_wave = ((size_t)L.enum_levels * (size_t)L.set_cap + (size_t)L.arena_cap) * sizeof(int32_t);
+        if (per_wave > 0) {
+            const size_t fit = (cap - ctl_b - trie_b) / per_wave;
+            if (fit < 1) {
+                set_error("one wavefront's scratch (" + std::to_string(per_wave) + " bytes for " +
+                          std::to_string(L.enum_levels) + " levels of up to " + std::to_string(L.set_cap) +
+                          " vertices) exceeds the fixed " + std::to_string(cap >> 20) + " MiB device array");
+                return PG_ENOMEM;
+            }
+            if ((size_t)L.grid > fit) L.grid = (int)fit;
+        }
+        char *ctl = static_cast<char *>(base);
+        char *trie = ctl + ctl_b;
+        int32_t *scratch = reinterpret_cast<int32_t *>(trie + trie_b);
+        unsigned long long *c = reinterpret_cast<unsigned long long *>(ctl);
+        PG_HIP(hipMemcpyAsync(trie, L.image.data(), L.image.size(), hipMemcpyHostToDevice, s));
+        PG_HIP(pg::launch_zero(c, kCtlWords, s));
+        const pg::KParams P = params(g, L, trie, c, scratch, LaunchArgs{}, n_plans, cfg);
+        PG_HIP(pg::launch_match(P, L.grid, L.variant, s));
+        unsigned long long h[kCtlWords];
+        PG_HIP(hipMemcpyAsync(h, c, sizeof(h), hipMemcpyDeviceToHost, s));
+        PG_HIP(hipStreamSynchronize(s));
+        return read_ctl(h, n_plans, counts, nullptr);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    }
+}
+
 pg_status pg_count(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts, void *hip_stream) {
     return pg_count_ex(g, plans, n_plans, counts, nullptr, nullptr, hip_stream);
 }

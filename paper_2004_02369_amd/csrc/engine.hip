@@ -30,6 +30,7 @@
 
 #include <climits>
 #include <cstdint>
+#include <mutex>
 
 #include "engine.hpp"
 
@@ -1462,6 +1463,53 @@ hipError_t launch_popcount(const uint32_t *bits, long long words, int rows, unsi
                            hipStream_t s) {
     const long long blocks = std::min<long long>(std::max<long long>(1, (words + 255) / 256), 1024);
     hipLaunchKernelGGL(popcount_rows, dim3((unsigned)blocks, (unsigned)rows), dim3(256), 0, s, bits, words, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------
+// Device memory for callers that cannot allocate (pg_count_noalloc): one
+// fixed array per device, [control block | program trie | per-wavefront
+// scratch], held from the library's first use on a device until the
+// process ends.  Every such call on a device shares it, so calls that
+// overlap on one device race.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+}  // namespace
+
+// The array's device address on the current device (looked up once per
+// device, with that device current; host code never uses the symbol
+// itself, only this address).
+hipError_t static_scratch(void **ptr, size_t *bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_static_ptr[dev] = p;
+    }
+    *ptr = g_static_ptr[dev];
+    *bytes = kStaticScratchBytes;
+    return hipSuccess;
+}
+
+// words 64-bit zeros from p on: a kernel rather than a memset, so the
+// clear is an ordinary kernel node for callers that capture the stream
+__global__ void __launch_bounds__(256) zero_words(unsigned long long *p, long long words) {
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+hipError_t launch_zero(unsigned long long *p, long long words, hipStream_t s) {
+    hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, s, p, words);
     return hipGetLastError();
 }
 

@@ -68,6 +68,15 @@ constexpr int kNumVariants = 4;
 
 hipError_t launch_match(const KParams &P, int grid, int variant, hipStream_t s);
 
+// Size of the fixed per-device array behind pg_count_noalloc.
+constexpr size_t kStaticScratchBytes = size_t(256) << 20;
+
+// Device address and size of that array on the current device.
+hipError_t static_scratch(void **ptr, size_t *bytes);
+
+// Zero `words` 64-bit words at p with a kernel on stream s.
+hipError_t launch_zero(unsigned long long *p, long long words, hipStream_t s);
+
 // out[r] += number of set bits in row r of `rows` bitmaps of `words` words each
 hipError_t launch_popcount(const uint32_t *bits, long long words, int rows, unsigned long long *out,
                            hipStream_t s);

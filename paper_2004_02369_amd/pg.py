@@ -88,7 +88,7 @@ MATCH_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes
 
 EXPORTS = ["pg_load_graph", "pg_graph_info", "pg_graph_csr", "pg_free_graph", "pg_plan_pattern",
            "pg_plan_pattern_ex", "pg_plan_info", "pg_free_plan", "pg_plan_programs", "pg_count", "pg_count_ex",
-           "pg_exists", "pg_enumerate", "pg_match", "pg_match_ex", "pg_root_tasks", "pg_enumerate_range",
+           "pg_count_noalloc", "pg_exists", "pg_enumerate", "pg_match", "pg_match_ex", "pg_root_tasks", "pg_enumerate_range",
            "pg_domain_sizes", "pg_job_workspace_size", "pg_submit", "pg_job_poll", "pg_job_finish",
            "pg_last_error"]
 
@@ -117,6 +117,7 @@ def lib():
     L.pg_free_plan.restype = None
     L.pg_plan_programs.argtypes = [vp, i32, vp, i64, ctypes.POINTER(i64)]
     L.pg_count.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(u64), vp]
+    L.pg_count_noalloc.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(u64), ctypes.POINTER(pg_run_config), vp]
     L.pg_count_ex.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(u64), ctypes.POINTER(pg_run_config),
                               ctypes.POINTER(pg_run_stats), vp]
     L.pg_exists.argtypes = [vp, vp, ctypes.POINTER(i32), vp]
@@ -320,6 +321,17 @@ def count_ex(graph: Graph, plans, stream=None, **knobs):
     _check(lib().pg_count_ex(graph._h, arr, len(plans), out, ctypes.byref(cfg), ctypes.byref(st),
                              _stream_ptr(stream)))
     return [int(x) for x in out], _stats(st)
+
+
+def count_noalloc(graph: Graph, plans, stream=None, **knobs):
+    """pg_count_noalloc: counts with no device allocation (a fixed device
+    array of the library holds the launch's memory)."""
+    plans = list(plans)
+    arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    out = (ctypes.c_uint64 * len(plans))()
+    cfg = run_config(**knobs)
+    _check(lib().pg_count_noalloc(graph._h, arr, len(plans), out, ctypes.byref(cfg), _stream_ptr(stream)))
+    return [int(x) for x in out]
 
 
 def _stats(st):
