@@ -51,7 +51,8 @@ typedef struct {
     int32_t hub_min_degree; /* rows of this degree or more also get a dense adjacency bitmap
                                (membership in one load instead of a binary search);
                                0 = 16, -1 = no bitmaps */
-    int32_t hub_budget_mib; /* HBM for those bitmaps, highest degrees first; 0 = 1024 */
+    int32_t hub_budget_mib; /* HBM for those bitmaps, highest degrees first; 0 = a sixteenth of
+                               the device memory (at least 1024 MiB) */
     int32_t reserved[5];    /* must be zero */
 } pg_options;
 
@@ -214,6 +215,9 @@ typedef struct {
 #define PG_RUN_LIGHT_KERNEL 8   /* run a long counting launch on the four-waves-per-SIMD build of
                                    the kernel (128 VGPRs, no spills) instead of the five-wave one;
                                    shorter launches always use it */
+#define PG_RUN_NO_SHARE 16      /* evaluate every level-2 node of an edge root on its own, without the
+                                   share groups that read several nodes' candidates from one
+                                   materialised set (Sec. 3.2: several patterns in one call) */
 
 typedef struct {
     double kernel_ms;        /* device time of the matching kernel (HIP events) */

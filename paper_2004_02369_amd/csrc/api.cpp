@@ -44,8 +44,8 @@ namespace {
 // and the launch shape.
 struct LaunchPlan {
     pg::Trie trie;
-    std::vector<char> image;  // nodes | anti-vertex checks | roots
-    size_t a_off = 0, r_off = 0;
+    std::vector<char> image;  // nodes | anti-vertex checks | roots | share-group lists
+    size_t a_off = 0, r_off = 0, x_off = 0;
     bool with_av = false;
     int variant = pg::kVarPlain;
     int grid = 0, chunk = 0;
@@ -235,7 +235,7 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         *out = nullptr;
         if (n < 1) { set_error("n must be >= 1"); return PG_EINVAL; }
         if (m < 0 || (m > 0 && (!src || !dst))) { set_error("bad edge arrays"); return PG_EINVAL; }
-        int64_t hub_min = kHubMinDegree, hub_budget = kHubBudgetBytes;
+        int64_t hub_min = kHubMinDegree, hub_budget = 0;  // 0: set from the device's memory below
         if (opt) {
             for (int i = 0; i < 5; i++)
                 if (opt->reserved[i]) { set_error("pg_options.reserved must be zero"); return PG_EINVAL; }
@@ -388,7 +388,10 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         if ((st = upload(&g->up, up, &g->device_bytes))) return st;
         // hub rows also as dense bitmaps: the highest-degree vertices (rank
         // order is degree order) with degree >= hub_min, within a budget
+        // (default: a sixteenth of the device's memory), built on the device
+        // from the uploaded rows
         {
+            if (hub_budget == 0) hub_budget = std::max<int64_t>(kHubBudgetBytes, (int64_t)(prop.totalGlobalMem / 16));
             const int64_t words = ((int64_t)n + 31) / 32;
             int32_t hs = n;
             while (hs > 0 && rp[hs] - rp[hs - 1] >= hub_min && (int64_t)(n - hs + 1) * words * 4 <= hub_budget)
@@ -398,12 +401,14 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
             g->hub_min_deg = hs < n ? rp[hs + 1] - rp[hs] : 0;
             for (int32_t r = hs; r < n; r++) g->hub_deg.push_back(rp[r + 1] - rp[r]);
             if (hs < n) {
-                std::vector<uint32_t> bits((size_t)(n - hs) * (size_t)words, 0u);
-                for (int32_t r = hs; r < n; r++) {
-                    uint32_t *b = bits.data() + (size_t)(r - hs) * (size_t)words;
-                    for (int64_t e = rp[r]; e < rp[r + 1]; e++) b[col[e] >> 5] |= 1u << (col[e] & 31);
+                const size_t nb = (size_t)(n - hs) * (size_t)words * sizeof(uint32_t);
+                if (hipMalloc(reinterpret_cast<void **>(&g->hub_bits), nb) != hipSuccess) {
+                    set_error("hipMalloc hub bitmaps");
+                    return PG_ENOMEM;
                 }
-                if ((st = upload(&g->hub_bits, bits, &g->device_bytes))) return st;
+                g->device_bytes += (int64_t)nb;
+                PG_HIP(pg::launch_hub_bits(g->rp, g->col, hs, n - hs, words, g->hub_bits, nullptr));
+                PG_HIP(hipDeviceSynchronize());
             }
         }
         if ((st = upload(&g->dperm, perm, &g->device_bytes))) return st;
@@ -596,13 +601,15 @@ void shape(const pg_graph *g, const pg_run_config *cfg, LaunchPlan &L, int mode,
     L.arena_cap = L.enum_levels ? kArenaInts : 0;
     L.scratch_ints = (size_t)L.grid * ((size_t)L.enum_levels * (size_t)L.set_cap + (size_t)L.arena_cap);
     const size_t nb = T.nodes.size() * sizeof(pg::Node), ab = T.avs.size() * sizeof(pg::AVCheck),
-                 rb = T.roots.size() * sizeof(int32_t);
+                 rb = T.roots.size() * sizeof(int32_t), xb = T.lists.size() * sizeof(int32_t);
     L.a_off = (nb + 15) & ~size_t(15);
     L.r_off = (L.a_off + ab + 15) & ~size_t(15);
-    L.image.assign(L.r_off + rb + 64, 0);
+    L.x_off = (L.r_off + rb + 15) & ~size_t(15);
+    L.image.assign(L.x_off + xb + 64, 0);
     std::memcpy(L.image.data(), T.nodes.data(), nb);
     std::memcpy(L.image.data() + L.a_off, T.avs.data(), ab);
     std::memcpy(L.image.data() + L.r_off, T.roots.data(), rb);
+    if (xb) std::memcpy(L.image.data() + L.x_off, T.lists.data(), xb);
 }
 
 pg_status check_trie(const pg::Trie &T) {
@@ -641,6 +648,7 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.nodes = reinterpret_cast<const pg::Node *>(trie_dev);
     P.avs = reinterpret_cast<const pg::AVCheck *>(static_cast<const char *>(trie_dev) + L.a_off);
     P.roots = reinterpret_cast<const int32_t *>(static_cast<const char *>(trie_dev) + L.r_off);
+    P.lists = reinterpret_cast<const int32_t *>(static_cast<const char *>(trie_dev) + L.x_off);
     P.cursor = ctl + kCtlCursor;
     P.counts = ctl + kCtlCounts;
     P.flags = reinterpret_cast<int32_t *>(ctl + kCtlFlags);

@@ -180,6 +180,25 @@ __device__ __forceinline__ int wave_scan_excl(int x, int lane, int *tot) {
     return inc - x;
 }
 
+// In a pass over laid-out segments, lane t holds an element of segment s(t)
+// with s non-decreasing in t, and segments of one prefix are adjacent, so
+// the lanes' prefixes form runs.  Adds each run's number of lanes with ok
+// to cnt[prefix]: one LDS atomic per run (distinct addresses) instead of
+// one per passing lane on the same address.
+template <class T>
+__device__ __forceinline__ void add_runs(T *cnt, int l, bool valid, bool ok, int lane) {
+    const int lp = __shfl_up(l, 1, 64);
+    const bool head = valid && (lane == 0 || lp != l);
+    const unsigned long long heads = __ballot(head), bal = __ballot(ok);
+    if (head && bal) {
+        const unsigned long long later = heads & ~((2ull << lane) - 1ull);  // 2 << 63 wraps to 0: no later head
+        const unsigned long long upto = later ? (1ull << __builtin_ctzll(later)) - 1ull : ~0ull;
+        const unsigned long long run = upto & ~((1ull << lane) - 1ull);
+        const int c = __popcll(bal & run);
+        if (c) atomicAdd(&cnt[l], (T)c);
+    }
+}
+
 // membership of e in the row of r.owner: one load for a hub (dense bitmap),
 // a binary search otherwise
 __device__ __forceinline__ bool in_row(const KParams &P, const RowRef &r, int32_t e) {
@@ -564,9 +583,15 @@ struct Ctx {
                 L.pmode[l] = 1;
                 int32_t c = dlen;
                 for (uint32_t s = N.excl; s; s &= s - 1) {
-                    int32_t v = val(__builtin_ctz(s), l);
+                    const int y = __builtin_ctz(s);
+                    int32_t v = val(y, l);
                     if (v <= lo || v >= hi) continue;
-                    if (!contains(dptr, dlen, v)) continue;
+                    // the pattern puts this image in the row and outside every difference row
+                    if ((N.excl_in >> y & 1u) && drv != kBaseOp) {
+                        c--;
+                        continue;
+                    }
+                    if (!in_range(P, dptr, dlen, downer, v)) continue;
                     bool in_d = false;
                     for (uint32_t t = N.t_diff; t && !in_d; t &= t - 1) in_d = in_row(P, row(__builtin_ctz(t), l), v);
                     if (!in_d) c--;
@@ -706,8 +731,8 @@ struct Ctx {
                         o[N.pv[x]] = P.perm[e];
                     }
                 }
-            } else if (ok) {
-                atomicAdd(&L.pcnt[l], 1u);
+            } else {
+                add_runs(L.pcnt, l, t < total, ok, lane);
             }
         }
         wsync();
@@ -766,8 +791,9 @@ struct Ctx {
     }
 
     // run every count / emit child of node `nid` over the candidates of
-    // level x held in setbuf(x) (length len), in batches of 64 prefixes
-    __device__ __forceinline__ void counts_over_set(int nid, int x, int32_t len) {
+    // level x held in setbuf(x) at positions [begin, end), in batches of 64
+    // prefixes
+    __device__ __forceinline__ void counts_over_set(int nid, int x, int32_t begin, int32_t end) {
         const Node &N = P.nodes[nid];
         const int cb = uni(N.child_begin), cc = uni(N.child_count);
         int first_enum = cc;
@@ -782,9 +808,9 @@ struct Ctx {
         plev0 = plev1 = -1;
         amode = 0;
         vl0 = x;
-        for (int32_t s = 0; s < len; s += kP) {
+        for (int32_t s = begin; s < end; s += kP) {
             if (stopped()) break;
-            const int np = min(kP, len - s);
+            const int np = min(kP, end - s);
             if (lane < np) {
                 const int32_t v = S[s + lane];
                 const long long o = P.rp[v];
@@ -844,6 +870,93 @@ struct Ctx {
         return E.kind == kEnum && !has_enum_child(E) && !(P.run_flags & PG_RUN_NO_TASK_BATCH);
     }
 
+    // Phase 2 of a batched expansion: the count / emit children of node nid
+    // over the candidates in [rb, re) of every parent's slice of the arena
+    // (lane t gives parent t's range), flattened 64 (parent, candidate)
+    // prefixes at a time.  A flat index belongs to the last parent whose
+    // range starts at or before it (a search over the lanes' starts).
+    __device__ __forceinline__ void expand_over(int nid, int x, int np, int32_t rb, int32_t re) {
+        const int32_t len = lane < np && re > rb ? re - rb : 0;
+        int ntot = 0;
+        const int32_t ms = wave_scan_excl(len, lane, &ntot);
+        const int32_t ms_key = lane < np ? ms : INT_MAX;
+        vl0 = x;
+        amode = 1;
+        const Node &N = P.nodes[nid];
+        const int cb = uni(N.child_begin), cc = uni(N.child_count);
+        for (int32_t s0 = 0; s0 < ntot; s0 += kP) {
+            const int np2 = min(kP, ntot - s0);
+            const int32_t idx = s0 + lane;
+            int t = 0;
+            for (int step = 32; step > 0; step >>= 1)
+                if (__shfl(ms_key, t + step) <= idx) t += step;
+            const int32_t tb = __shfl(rb, t), tm = __shfl(ms, t);
+            if (lane < np2) {
+                const int32_t k = tb + (idx - tm);
+                const int32_t v = arena[L.tstart[t] + k];
+                const long long o = P.rp[v];
+                L.ptask[lane] = t;
+                L.pidx[lane] = k;
+                L.pv0[lane] = v;
+                L.po0[lane] = (int32_t)o;
+                L.pl0[lane] = (int32_t)(P.rp[v + 1] - o);
+                L.pu0[lane] = P.up[v];
+            }
+            for (int c = 0; c < cc; c++) {
+                if (lane < np2) L.pmode[lane] = 0;
+                wsync();
+                count_batch(P.nodes[cb + c], np2);
+            }
+        }
+        amode = 0;
+        vl0 = -1;
+        // the next round's setup reads parent slots through ptask
+        if (lane < np) L.ptask[lane] = lane;
+        wsync();
+    }
+
+    // A share group's count member M: lane t's parent has n candidates in
+    // M's range (mine: the lane holds a parent), so it adds
+    // C(n, group) * mult to M's plan.
+    __device__ __forceinline__ void count_member(const Node &M, int32_t n, bool mine) {
+        unsigned long long contrib = 0;
+        bool ovf = false;
+        if (mine && n > 0) {
+            contrib = choose((unsigned long long)n, M.group, &ovf);
+            unsigned long long q;
+            if (__builtin_mul_overflow(contrib, M.mult, &q)) ovf = true;
+            contrib = q;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(contrib, off);
+            const unsigned long long sum = contrib + o;
+            if (sum < contrib) ovf = true;
+            contrib = sum;
+        }
+        if (__ballot(ovf) && lane == 0) atomicOr(P.flags, 1);
+        if (lane == M.plan) {
+            const unsigned long long sum = acc + contrib;
+            if (sum < acc) atomicOr(P.flags, 1);
+            acc = sum;
+            if (P.mode == kModeExists && sum > 0) {
+                atomicOr(P.flags + 1, 1);
+                L.stop = 1;
+            }
+        }
+    }
+
+    // the positions [*rb, *re) of the sorted set S (n elements) that lie in
+    // node M's id range for prefix l (-1: the fixed assignment)
+    __device__ __forceinline__ void member_range(const Node &M, int l, const int32_t *S, int32_t n, int32_t *rb,
+                                                 int32_t *re) const {
+        int32_t lo = -1, hi = INT_MAX;
+        for (uint32_t s = M.lo; s; s &= s - 1) lo = max(lo, val(__builtin_ctz(s), l));
+        for (uint32_t s = M.hi; s; s &= s - 1) hi = min(hi, val(__builtin_ctz(s), l));
+        *rb = lo < 0 ? 0 : lower_bound(S, n, lo + 1);
+        *re = hi == INT_MAX ? n : lower_bound(S, n, hi);
+        if (*re < *rb) *re = *rb;
+    }
+
     // Enumeration node E whose children are all count / emit nodes, for a
     // batch of np parents at once (slots 0..np-1: root tasks with plev0/1 =
     // levels 0/1, or elements of a materialised set with plev0 = its
@@ -854,6 +967,8 @@ struct Ctx {
     __device__ __forceinline__ void leaf_batch(int eid, int np, unsigned long long okmask) {
         const Node &E = P.nodes[eid];
         const int x = E.level;
+        // a share group's leader lists its members (0 for any other node)
+        const int mcount = uni(E.list_count), mbegin = uni(E.list_begin);
         if (lane < np) L.ptask[lane] = lane;
         wsync();
         vl0 = -1;
@@ -980,10 +1095,8 @@ struct Ctx {
                     pass = test_direct(E, x, l, L.pdrv[l], e, dec(L.boff[l]), L.blen[l]);
                 }
                 const unsigned long long bal = __ballot(pass);
-                if (pass) {
-                    arena[out_n + (int32_t)__popcll(bal & ((1ull << lane) - 1ull))] = e;
-                    atomicAdd(&L.tcnt[l], 1);
-                }
+                if (pass) arena[out_n + (int32_t)__popcll(bal & ((1ull << lane) - 1ull))] = e;
+                add_runs(L.tcnt, l, t < total, pass, lane);
                 out_n += (int32_t)__popcll(bal);
             }
             wsync();
@@ -994,44 +1107,20 @@ struct Ctx {
             if (lane < np) L.tstart[lane] = st;
             if (lane == 0) L.tstart[np] = ntot;
             wsync();
-            vl0 = x;
-            amode = 1;
-            const int cb = uni(E.child_begin), cc = uni(E.child_count);
-            for (int32_t s0 = 0; s0 < ntot; s0 += kP) {
-                const int np2 = min(kP, ntot - s0);
-                if (lane < np2) {
-                    const int32_t idx = s0 + lane;
-                    // parent holding arena index idx: last t with tstart[t] <= idx
-                    int t_lo = 0, t_n = np;
-                    while (t_n > 1) {
-                        const int half = t_n >> 1;
-                        if (L.tstart[t_lo + half] <= idx) {
-                            t_lo += half;
-                            t_n -= half;
-                        } else {
-                            t_n = half;
-                        }
-                    }
-                    const int32_t v = arena[idx];
-                    const long long o = P.rp[v];
-                    L.ptask[lane] = t_lo;
-                    L.pidx[lane] = idx - L.tstart[t_lo];
-                    L.pv0[lane] = v;
-                    L.po0[lane] = (int32_t)o;
-                    L.pl0[lane] = (int32_t)(P.rp[v + 1] - o);
-                    L.pu0[lane] = P.up[v];
-                }
-                for (int c = 0; c < cc; c++) {
-                    if (lane < np2) L.pmode[lane] = 0;
-                    wsync();
-                    count_batch(P.nodes[cb + c], np2);
+            if (mcount == 0) {
+                expand_over(eid, x, np, 0, tc);
+            } else {
+                // a share group's leader: every member reads its own range
+                // out of each parent's slice
+                for (int k = 0; k < mcount; k++) {
+                    const int mid = uni(P.lists[mbegin + k]);
+                    const Node &M = P.nodes[mid];
+                    int32_t rb = 0, re = 0;
+                    if (lane < np && tc > 0) member_range(M, lane, arena + st, tc, &rb, &re);
+                    if (M.kind == kEnum) expand_over(mid, x, np, rb, re);
+                    else count_member(M, re - rb, lane < np);
                 }
             }
-            amode = 0;
-            vl0 = -1;
-            // the next round's setup reads parent slots through ptask
-            if (lane < np) L.ptask[lane] = lane;
-            wsync();
         }
         // parents too large for the arena: one at a time into setbuf(x)
         if (bigmask) {
@@ -1045,7 +1134,21 @@ struct Ctx {
                 const int32_t len = materialise(E);
                 if (lane == 0) L.set_len[x] = len;
                 wsync();
-                if (len > 0) counts_over_set(eid, x, len);
+                if (mcount == 0) {
+                    if (len > 0) counts_over_set(eid, x, 0, len);
+                } else {
+                    for (int k = 0; k < mcount; k++) {
+                        const int mid = uni(P.lists[mbegin + k]);
+                        const Node &M = P.nodes[mid];
+                        int32_t rb, re;
+                        member_range(M, -1, setbuf(x), len, &rb, &re);
+                        if (M.kind == kEnum) {
+                            if (re > rb) counts_over_set(mid, x, rb, re);
+                        } else {
+                            count_member(M, re - rb, lane == 0);
+                        }
+                    }
+                }
                 plev0 = sp0;
                 plev1 = sp1;
             }
@@ -1107,7 +1210,7 @@ struct Ctx {
             if (lane == 0) L.set_len[2] = len;
             wsync();
             if (len == 0) continue;
-            counts_over_set(e0, 2, len);
+            counts_over_set(e0, 2, 0, len);
             leaf_children_over_set(e0, 2, len);
             if (!has_deep_enum_child(E0)) continue;
             // stack of enumeration frames
@@ -1149,7 +1252,7 @@ struct Ctx {
                 if (lane == 0) L.set_len[x + 1] = len2;
                 wsync();
                 if (len2 == 0) continue;
-                counts_over_set(nid2, x + 1, len2);
+                counts_over_set(nid2, x + 1, 0, len2);
                 leaf_children_over_set(nid2, x + 1, len2);
                 if (has_deep_enum_child(P.nodes[nid2])) {
                     if (lane == 0) {
@@ -1274,6 +1377,9 @@ __device__ __forceinline__ void match_body(const KParams P) {
         }
     }
     wsync();
+    // share groups apply to batched count and existence launches (not to
+    // emission, domain marks, or level-2 expansion one root task at a time)
+    const bool share_on = !(P.run_flags & (PG_RUN_NO_TASK_BATCH | PG_RUN_NO_SHARE)) && !P.mark && P.mode != kModeEmit;
     // this launch's window of root tasks: [t_lo, t_hi) of the edge tasks
     // followed by the vertex tasks
     const long long t_lo = P.task_begin;
@@ -1360,9 +1466,18 @@ __device__ __forceinline__ void match_body(const KParams P) {
                         any_enum = true;
                         break;
                     }
+                    if (share_on && N.share >= 0) continue;  // counted by its share group
                     if (lane < np) L.pmode[lane] = okr ? (int8_t)0 : (int8_t)-1;
                     wsync();
                     C.count_batch(N, np);
+                }
+                // share groups: one materialisation per root task for all members
+                if (share_on && edge_phase) {
+                    const int lb = uni(R.list_begin), lc = uni(R.list_count);
+                    for (int g = 0; g < lc; g++) {
+                        if (C.stopped()) break;
+                        C.leaf_batch(uni(P.lists[lb + g]), np, okmask);
+                    }
                 }
                 if (!any_enum || !edge_phase) {
                     C.plev0 = C.plev1 = -1;
@@ -1377,6 +1492,7 @@ __device__ __forceinline__ void match_body(const KParams P) {
                         any_deep = true;
                         continue;
                     }
+                    if (share_on && P.nodes[eid].share >= 0) continue;  // expanded by its share group
                     if (C.stopped()) break;
                     C.leaf_batch(eid, np, okmask);
                 }
@@ -1510,6 +1626,28 @@ __global__ void __launch_bounds__(256) zero_words(unsigned long long *p, long lo
 
 hipError_t launch_zero(unsigned long long *p, long long words, hipStream_t s) {
     hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, s, p, words);
+    return hipGetLastError();
+}
+
+// Hub bitmaps: row r of bits (words 32-bit words) is the adjacency of
+// vertex first + r.  One workgroup per row: clear it, then set the bit of
+// every neighbour (rows are sorted, but neighbours share words, so OR).
+__global__ void __launch_bounds__(256) build_hub_bits(const int64_t *rp, const int32_t *col, int32_t first,
+                                                      long long words, uint32_t *bits) {
+    const int32_t v = first + (int32_t)blockIdx.x;
+    uint32_t *row = bits + (long long)blockIdx.x * words;
+    for (long long i = threadIdx.x; i < words; i += blockDim.x) row[i] = 0u;
+    __syncthreads();
+    for (long long e = rp[v] + threadIdx.x; e < rp[v + 1]; e += blockDim.x) {
+        const int32_t c = col[e];
+        atomicOr(row + (c >> 5), 1u << (c & 31));
+    }
+}
+
+hipError_t launch_hub_bits(const int64_t *rp, const int32_t *col, int32_t first, int32_t rows, long long words,
+                           uint32_t *bits, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(build_hub_bits, dim3((unsigned)rows), dim3(256), 0, s, rp, col, first, words, bits);
     return hipGetLastError();
 }
 

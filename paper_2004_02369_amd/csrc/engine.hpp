@@ -24,6 +24,7 @@ struct KParams {
     const Node *nodes;
     const AVCheck *avs;
     const int32_t *roots;
+    const int32_t *lists;      // share groups (leaders of a root, members of a leader)
     unsigned long long *cursor;
     unsigned long long *counts;
     int32_t *flags;            // [0] overflow, [1] stop, [2] time limit reached
@@ -67,6 +68,11 @@ enum Variant : int { kVarPlain = 0, kVarPre = 1, kVarAV = 2, kVarLight = 3 };
 constexpr int kNumVariants = 4;
 
 hipError_t launch_match(const KParams &P, int grid, int variant, hipStream_t s);
+
+// Dense adjacency bitmaps of the rows of vertices first .. first+rows-1
+// (words 32-bit words each) from the CSR, on stream s.
+hipError_t launch_hub_bits(const int64_t *rp, const int32_t *col, int32_t first, int32_t rows, long long words,
+                           uint32_t *bits, hipStream_t s);
 
 // Size of the fixed per-device array behind pg_count_noalloc.
 constexpr size_t kStaticScratchBytes = size_t(256) << 20;

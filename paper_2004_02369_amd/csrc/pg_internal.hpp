@@ -46,6 +46,7 @@ struct Node {
     uint32_t lo;       // ... and larger than these images (partial / matching order)
     uint32_t hi;       // ... and smaller than these
     uint32_t excl;     // ... and different from these (injectivity not implied otherwise)
+    uint32_t excl_in;  // excl levels whose images certainly lie in every isect row and no diff row
     uint32_t t_isect;  // isect levels still to test once the base set is used
     uint32_t t_diff;   // diff levels still to test once the base set is used
     int32_t base;      // materialised ancestor level whose set contains every candidate; -1 none
@@ -62,11 +63,23 @@ struct Node {
     int32_t label1;
     int8_t pv[kMaxLevels];  // emit: pattern vertex matched at each level
     int32_t anchor_level;   // count: level holding the plan's anchored vertex (-1 none)
+    // share groups (siblings under an edge root with one set operation and
+    // different id ranges): a member's `share` is its group's leader, an
+    // enumeration node outside the tree that holds the widest range; a
+    // leader lists its members, an edge root its leaders, at
+    // lists[list_begin .. list_begin + list_count)
+    int32_t share;
+    int32_t list_begin;
+    int32_t list_count;
 };
 
 // A program: one matching order with its completion, as a sequence of levels.
 struct Level {
     uint32_t isect = 0, diff = 0, lo = 0, hi = 0, excl = 0;
+    // excluded levels whose pattern vertex has a true edge to every isect
+    // level's and an anti-edge to every diff level's (and the label): their
+    // images are in every isect row and in no diff row of any valid prefix
+    uint32_t excl_in = 0;
     uint32_t t_isect = 0, t_diff = 0;
     int32_t base = -1;
     int32_t label = -1;
@@ -99,6 +112,7 @@ struct Trie {
     std::vector<Node> nodes;
     std::vector<AVCheck> avs;
     std::vector<int32_t> roots;   // node ids of root nodes
+    std::vector<int32_t> lists;   // share groups: leaders of a root, members of a leader (node ids)
     int32_t max_level = 0;        // deepest level index + 1
     bool has_vertex_root = false;
     bool has_edge_root = false;

@@ -568,6 +568,16 @@ BuiltProgram build_program(const Typed &t, const std::vector<int> &core_seq, uin
             if (lt[u] >> w & 1u) L.hi |= bit;
         }
         L.excl = ((1u << x) - 1u) & ~(L.isect | L.lo | L.hi);
+        for (int y = 0; y < x && L.isect; y++) {
+            if (!(L.excl >> y & 1u)) continue;
+            const int w = seq[y];
+            bool in = t.lab[u] < 0 || t.lab[w] == t.lab[u];
+            for (int z = 0; z < x && in; z++) {
+                if ((L.isect >> z & 1u) && !(t.E[w] >> seq[z] & 1u)) in = false;
+                if ((L.diff >> z & 1u) && !(t.A[w] >> seq[z] & 1u)) in = false;
+            }
+            if (in) L.excl_in |= 1u << y;
+        }
         L.label = t.lab[u];
         L.pv = u;
         L.group = group;
@@ -780,13 +790,14 @@ struct HostNode {
     std::vector<AVCheck> avs;
     std::vector<int> children;
     std::string key;
+    bool product = false;  // a factor node, or the count node closing a product
 };
 
 std::string node_key(const Node &n, const std::vector<AVCheck> &avs) {
     std::string s;
     auto put = [&](uint64_t v) { s.append(reinterpret_cast<const char *>(&v), sizeof(v)); };
     put((uint64_t)n.kind); put((uint64_t)n.level); put(n.isect); put(n.diff); put(n.lo); put(n.hi);
-    put(n.excl); put(n.t_isect); put(n.t_diff); put((uint64_t)(int64_t)n.base);
+    put(n.excl); put(n.excl_in); put(n.t_isect); put(n.t_diff); put((uint64_t)(int64_t)n.base);
     put((uint64_t)(int64_t)n.label); put((uint64_t)n.group); put((uint64_t)(int64_t)n.label0);
     put((uint64_t)(int64_t)n.label1);
     if (n.kind == kCount || n.kind == kEmit || n.kind == kFactor || n.anchor_level >= 0) {
@@ -814,10 +825,76 @@ Node blank_node() {
     n.mult = 1;
     for (int i = 0; i < kMaxLevels; i++) n.pv[i] = -1;
     n.anchor_level = -1;
+    n.share = -1;
     return n;
 }
 
 }  // namespace
+
+// Share groups.  Children of an edge root at level 2 that apply the same set
+// operation (true-edge rows, anti-edge rows, exclusions) and differ only in
+// their id ranges -- count nodes, and enumeration nodes whose children only
+// count -- form a group when there are two or more of them.  The group gets
+// a leader: an enumeration node outside the tree with the ranges every
+// member shares (the intersection of their lo / hi level masks), whose
+// candidates contain every member's.  The engine materialises the leader's
+// candidates once per root task and reads each member's range out of them.
+// Members with a base set, a label, anti-vertex checks, a domain anchor or
+// a part in a product are left alone.
+void share_groups(Trie &T, const std::vector<bool> &product) {
+    const size_t n0 = T.nodes.size();
+    for (size_t r = 0; r < T.roots.size(); r++) {
+        const int rid = T.roots[r];
+        if (T.nodes[rid].kind != kRootEdge) continue;
+        const Node R = T.nodes[rid];
+        std::map<std::vector<uint32_t>, std::vector<int>> groups;
+        for (int c = R.child_begin; c < R.child_begin + R.child_count; c++) {
+            const Node &N = T.nodes[c];
+            if (N.level != 2 || N.base >= 0 || N.label >= 0 || N.av_count || N.anchor_level >= 0 || product[c])
+                continue;
+            if (N.kind == kEnum) {
+                bool leaf = true;
+                for (int d = N.child_begin; d < N.child_begin + N.child_count; d++)
+                    if (T.nodes[d].kind == kEnum) leaf = false;
+                if (!leaf) continue;
+            } else if (N.kind != kCount) {
+                continue;
+            }
+            groups[{N.isect, N.diff, N.excl, N.t_isect, N.t_diff}].push_back(c);
+        }
+        std::vector<int32_t> leaders;
+        for (auto &kv : groups) {
+            const std::vector<int> &mem = kv.second;
+            if (mem.size() < 2) continue;
+            Node L = T.nodes[mem[0]];
+            L.kind = kEnum;
+            L.group = 1;
+            L.plan = 0;
+            L.mult = 1;
+            L.child_begin = L.child_count = 0;
+            for (int m : mem) {
+                L.lo &= T.nodes[m].lo;
+                L.hi &= T.nodes[m].hi;
+            }
+            L.share = -1;
+            L.list_begin = (int32_t)T.lists.size();
+            L.list_count = (int32_t)mem.size();
+            const int lid = (int)T.nodes.size();
+            for (int m : mem) {
+                T.lists.push_back(m);
+                T.nodes[m].share = lid;
+            }
+            T.nodes.push_back(L);
+            leaders.push_back(lid);
+        }
+        if (!leaders.empty()) {
+            T.nodes[rid].list_begin = (int32_t)T.lists.size();
+            T.nodes[rid].list_count = (int32_t)leaders.size();
+            for (int32_t l : leaders) T.lists.push_back(l);
+        }
+    }
+    (void)n0;
+}
 
 Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
     std::vector<HostNode> H;
@@ -869,6 +946,7 @@ Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
                 h.n.kind = kind;
                 h.n.level = x;
                 h.n.isect = L.isect; h.n.diff = L.diff; h.n.lo = L.lo; h.n.hi = L.hi; h.n.excl = L.excl;
+                h.n.excl_in = L.excl_in;
                 h.n.t_isect = L.t_isect; h.n.t_diff = L.t_diff; h.n.base = L.base;
                 h.n.label = L.label;
                 h.n.group = L.group;
@@ -890,6 +968,7 @@ Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
             for (const Level &L : p.factors) {
                 HostNode h = level_node(L, F, kFactor);
                 h.key = node_key(h.n, h.avs) + own;
+                h.product = true;
                 child(cur, std::move(h));
             }
             if (F > H[cur].n.level) {
@@ -898,6 +977,7 @@ Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
                 h.n.k = plans[pi]->k;
                 for (int y = 0; y <= F; y++) h.n.pv[y] = (int8_t)p.lev[y].pv;
                 h.key = node_key(h.n, h.avs) + own;
+                h.product = !own.empty();
                 child(cur, std::move(h));
             }
         }
@@ -938,6 +1018,11 @@ Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
             T.roots.push_back(id2[roots[r]]);
             if (H[roots[r]].n.kind == kRootVertex) T.has_vertex_root = true;
             else T.has_edge_root = true;
+        }
+        if (!emit) {
+            std::vector<bool> product(T.nodes.size(), false);
+            for (size_t i = 0; i < order2.size(); i++) product[i] = H[order2[i]].product;
+            share_groups(T, product);
         }
     }
     // every program ends in its own leaf (count programs are merged before,

@@ -12,6 +12,8 @@
                                                      # (64M edges): each alone (time, merge-model bytes), then batched
     python -m paper_2004_02369_amd.measure rows      # achievable HBM read bandwidth, and row-pair intersections
                                                      # on the R-MAT scale 22 rows by variant and row length
+    python -m paper_2004_02369_amd.measure hubs      # the benchmark batch on R-MAT scale 22 with more or fewer
+                                                     # rows held as bitmaps (hub bitmap budget sweep)
 """
 from __future__ import annotations
 
@@ -253,6 +255,34 @@ def rows(args, pg, gg, pt):
     print(json.dumps(out), flush=True)
 
 
+def hubs(args, pg, gg, pt):
+    """The benchmark's batch (serving count queries) on the serving graph
+    loaded with several hub-bitmap budgets: rows held as bitmaps, HBM held,
+    batch and per-pattern kernel time.  Counts must not change."""
+    from . import serve
+    edges = gg.workload(args.workload)
+    names = ["triangle", "wedge", "induced_wedge", "clique4", "book3", "cricket"]
+    ref = None
+    for mib in [int(x) for x in args.budgets.split(",")]:
+        t = time.perf_counter()
+        G = pg.load_graph(*edges, device=0, hub_budget_mib=mib)
+        load_s = time.perf_counter() - t
+        q = {x.name: x for x in serve.catalogue(pg, pt)}
+        plans = [q[n].plans[0] for n in names]
+        c, _ = pg.count_ex(G, plans)
+        ms = min(pg.count_ex(G, plans)[1]["kernel_ms"] for _ in range(2))
+        if ref is None:
+            ref = c
+        assert c == ref, "counts changed with the bitmap budget"
+        single = {n: pg.count_ex(G, [p])[1]["kernel_ms"] for n, p in zip(names, plans)}
+        rec = {"measure": "hubs", "workload": args.workload, "budget_mib": mib, "hub_rows": G.hub_count,
+               "hub_min_degree": G.hub_min_degree, "device_bytes": G.device_bytes, "load_s": load_s,
+               "batch_kernel_ms": ms, "single_kernel_ms": single}
+        _say(json.dumps(rec))
+        print(json.dumps(rec), flush=True)
+        del G
+
+
 def small(args, pg, gg, pt):
     """Launch-bound regime: the six induced 4-motifs on ER 2k/20k, one
     batched launch against six launches, best of several repetitions."""
@@ -276,9 +306,10 @@ def small(args, pg, gg, pt):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion", "c1", "c3", "c5", "rows"])
+    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion", "c1", "c3", "c5", "rows", "hubs"])
     ap.add_argument("--pairs", type=int, default=2_000_000)
     ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--budgets", default="1024,4096,16384,32768")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--limit-ms", type=int, default=600000)
     ap.add_argument("--tune-budget", type=float, default=60.0)
@@ -301,6 +332,9 @@ def main(argv=None):
     elif args.what == "c3":
         args.workload = args.workload or "rmat20_16m"
         c3(args, pg, gg, pt)
+    elif args.what == "hubs":
+        args.workload = args.workload or "rmat22_64m"
+        hubs(args, pg, gg, pt)
     elif args.what == "rows":
         args.workload = args.workload or "rmat22_64m"
         rows(args, pg, gg, pt)

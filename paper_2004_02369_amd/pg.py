@@ -23,7 +23,7 @@ PG_OK, PG_STOPPED = 0, 1
 PG_EINVAL, PG_ENOMEM, PG_EDEVICE, PG_EOVERFLOW, PG_EUNSUPPORTED, PG_ETIMEDOUT = -1, -2, -3, -4, -5, -6
 PG_EDGE, PG_ANTI_EDGE = 0, 1
 PG_PLAN_AUTO, PG_PLAN_LINEAR_EXT, PG_PLAN_PARTIAL_ORDER = 0, 1, 2
-PG_RUN_COUNT_BYTES, PG_RUN_NO_MODE_B, PG_RUN_NO_TASK_BATCH, PG_RUN_LIGHT_KERNEL = 1, 2, 4, 8
+PG_RUN_COUNT_BYTES, PG_RUN_NO_MODE_B, PG_RUN_NO_TASK_BATCH, PG_RUN_LIGHT_KERNEL, PG_RUN_NO_SHARE = 1, 2, 4, 8, 16
 PG_JOB_COUNT, PG_JOB_EXISTS = 0, 1
 
 _STATUS = {PG_EINVAL: "EINVAL", PG_ENOMEM: "ENOMEM", PG_EDEVICE: "EDEVICE", PG_EOVERFLOW: "EOVERFLOW",

@@ -302,3 +302,28 @@ def test_anti_vertex_p7_medium(pg, orc):
     want = orc.count(orc.Graph.from_tuple(g), pt.P7_TRIANGLE_NO_K4)
     assert pg.count(G(pg, g), pg.plan_pattern(pt.P7_TRIANGLE_NO_K4)) == want
     assert pg.count(G(pg, gg.complete(9)), pg.plan_pattern(pt.P7_TRIANGLE_NO_K4)) == 0
+
+
+def test_share_groups_equal_oracle(pg, orc):
+    """Plans whose level-2 nodes apply one set operation over different id
+    ranges share one materialisation per root task (share groups): counts
+    with sharing, without it (PG_RUN_NO_SHARE), one launch per plan, and
+    under grids, claims and batching limits that send parents down the
+    one-at-a-time path, all equal the oracle's."""
+    g = gg.chung_lu(900, 6000, 2.1, 70.0, seed=44)
+    say("share groups, chung_lu 900/6000")
+    Gd = G(pg, g)
+    specs = ([pt.clique(3), pt.star(3), pt.star(3, induced=True), pt.clique(4), pt.clique(5)]
+             + list(pt.EDGE_CORE_5.values()) + pt.all_vertex_induced(4) + [DIAMOND, pt.P8_INDUCED_DIAMOND])
+    plans = [pg.plan_pattern(s) for s in specs]
+    og = orc.Graph.from_tuple(g)
+    want = [orc.count(og, s) for s in specs]
+    assert pg.count(Gd, plans) == want
+    assert pg.count(Gd, plans, flags=pg.PG_RUN_NO_SHARE) == want
+    assert [pg.count(Gd, p) for p in plans] == want
+    for grid, chunk, bma, flags in [(1, 1, 0, 0), (37, 5, 1, 0), (512, 64, 2, 0), (64, 16, 0, pg.PG_RUN_NO_MODE_B),
+                                    (256, 8, 0, pg.PG_RUN_COUNT_BYTES), (128, 4, 0, pg.PG_RUN_NO_TASK_BATCH)]:
+        say("share perturbation", grid, chunk, bma, flags)
+        assert pg.count(Gd, plans, grid_waves=grid, chunk=chunk, batch_max_avg=bma, flags=flags) == want
+    # existence of a share-group member stops early and finds the same answer
+    assert pg.exists(Gd, pg.plan_pattern(pt.EDGE_CORE_5["book3"])) is (want[specs.index(pt.EDGE_CORE_5["book3"])] > 0)
