@@ -136,20 +136,27 @@ __device__ __forceinline__ int32_t restrict_row(const RowRef &r, int32_t lo, int
     return b;
 }
 
-// C(n, j) exactly.  After step t, r = C(n - j + t, t); the product r * f is
-// formed in 128 bits, so only a result of 2^64 or more sets the flag (the
-// quotient of each step is an integer, C(n-j+t, t) = C(n-j+t-1, t-1) * f / t).
+// C(n, j) exactly.  After step t, r = C(n - j + t, t) (each step's quotient
+// is an integer: C(n-j+t, t) = C(n-j+t-1, t-1) * f / t).  The product r * f
+// is formed in 64 bits when it fits and in 128 bits otherwise, so only a
+// result of 2^64 or more sets the flag.
 __device__ __forceinline__ unsigned long long choose(unsigned long long n, int j, bool *ovf) {
     if ((long long)j > (long long)n) return 0;
+    if (j == 1) return n;
     unsigned long long r = 1;
     for (int t = 1; t <= j; t++) {
         const unsigned long long f = n - (unsigned long long)j + (unsigned long long)t;
-        const unsigned __int128 q = (unsigned __int128)r * f / (unsigned __int128)t;
-        if (q >> 64) {
-            *ovf = true;
-            return 0;
+        unsigned long long q;
+        if (!__builtin_mul_overflow(r, f, &q)) {
+            r = q / (unsigned long long)t;
+        } else {
+            const unsigned __int128 w = (unsigned __int128)r * f / (unsigned __int128)t;
+            if (w >> 64) {
+                *ovf = true;
+                return 0;
+            }
+            r = (unsigned long long)w;
         }
-        r = (unsigned long long)q;
     }
     return r;
 }
@@ -803,8 +810,16 @@ struct Ctx {
                 break;
             }
         if (first_enum == 0) return;
-        const int32_t *S = setbuf(x);
         const int sp0 = plev0, sp1 = plev1;
+        if (N.flags & kIndepCounts) {
+            // one parent (the fixed assignment): its candidates each add the same term
+            plev0 = plev1 = -1;
+            indep_counts(N, -1, end - begin, lane == 0);
+            plev0 = sp0;
+            plev1 = sp1;
+            return;
+        }
+        const int32_t *S = setbuf(x);
         plev0 = plev1 = -1;
         amode = 0;
         vl0 = x;
@@ -877,6 +892,11 @@ struct Ctx {
     // range starts at or before it (a search over the lanes' starts).
     __device__ __forceinline__ void expand_over(int nid, int x, int np, int32_t rb, int32_t re) {
         const int32_t len = lane < np && re > rb ? re - rb : 0;
+        if (P.nodes[nid].flags & kIndepCounts) {
+            // every candidate adds the same term: no per-candidate pass
+            indep_counts(P.nodes[nid], lane, len, lane < np);
+            return;
+        }
         int ntot = 0;
         const int32_t ms = wave_scan_excl(len, lane, &ntot);
         const int32_t ms_key = lane < np ? ms : INT_MAX;
@@ -927,6 +947,41 @@ struct Ctx {
             if (__builtin_mul_overflow(contrib, M.mult, &q)) ovf = true;
             contrib = q;
         }
+        add_to_plan(M.plan, contrib, ovf);
+    }
+
+    // Count children of an enumeration node flagged kIndepCounts: every
+    // candidate of the node adds the same term, C(|row| - excluded, group)
+    // * mult, the node's own image being one of the excluded ones (the
+    // pattern puts it in the row).  Lane l (mine) holds a parent with n
+    // candidates; l is also the prefix slot val() and row() read.
+    __device__ __forceinline__ void indep_counts(const Node &E, int l, int32_t n, bool mine) {
+        const int x = E.level;
+        const int cb = uni(E.child_begin), cc = uni(E.child_count);
+        for (int c = 0; c < cc; c++) {
+            const Node &N = P.nodes[cb + c];
+            unsigned long long contrib = 0;
+            bool ovf = false;
+            if (mine && n > 0) {
+                const RowRef r = row(__builtin_ctz(N.t_isect), l);
+                int32_t k = r.n;
+                for (uint32_t s = N.excl; s; s &= s - 1) {
+                    const int y = __builtin_ctz(s);
+                    if (y == x || (N.excl_in >> y & 1u)) k--;
+                    else if (in_row(P, r, val(y, l))) k--;
+                }
+                unsigned long long q;
+                contrib = choose((unsigned long long)max(k, 0), N.group, &ovf);
+                if (__builtin_mul_overflow(contrib, N.mult, &q)) ovf = true;
+                if (__builtin_mul_overflow(q, (unsigned long long)n, &contrib)) ovf = true;
+            }
+            add_to_plan(N.plan, contrib, ovf);
+        }
+    }
+
+    // add every lane's contrib to plan `plan` (wave reduction, overflow flag,
+    // existence stop); the sum lands in lane plan's accumulator
+    __device__ __forceinline__ void add_to_plan(int plan, unsigned long long contrib, bool ovf) {
         for (int off = 32; off > 0; off >>= 1) {
             const unsigned long long o = __shfl_xor(contrib, off);
             const unsigned long long sum = contrib + o;
@@ -934,7 +989,7 @@ struct Ctx {
             contrib = sum;
         }
         if (__ballot(ovf) && lane == 0) atomicOr(P.flags, 1);
-        if (lane == M.plan) {
+        if (lane == plan) {
             const unsigned long long sum = acc + contrib;
             if (sum < acc) atomicOr(P.flags, 1);
             acc = sum;

@@ -71,7 +71,16 @@ struct Node {
     int32_t share;
     int32_t list_begin;
     int32_t list_count;
+    int32_t flags;     // kIndepCounts
 };
+
+// Enumeration node flag: every child is a count node whose candidates do not
+// depend on this node's vertex except through excluding it, and the pattern
+// puts that vertex inside the count's one row (excl_in), with no id range,
+// base set, difference row, label, anti-vertex check or domain anchor.  Each
+// candidate of this node then adds the same C(|row| - excluded, group), so a
+// parent's total is its number of candidates times that term.
+constexpr int32_t kIndepCounts = 1;
 
 // A program: one matching order with its completion, as a sequence of levels.
 struct Level {

@@ -831,6 +831,26 @@ Node blank_node() {
 
 }  // namespace
 
+// Enumeration nodes whose count children each add a term that does not
+// depend on the node's own vertex (see kIndepCounts): the count child has one
+// row of an earlier level as its only operand, no range, and excludes this
+// level's image, which the pattern places inside that row.
+void mark_independent_counts(Trie &T, const std::vector<bool> &product) {
+    for (size_t i = 0; i < T.nodes.size(); i++) {
+        Node &E = T.nodes[i];
+        if (E.kind != kEnum || E.child_count == 0 || E.av_count) continue;
+        const int x = E.level;
+        bool ok = true;
+        for (int c = E.child_begin; c < E.child_begin + E.child_count && ok; c++) {
+            const Node &N = T.nodes[c];
+            ok = N.kind == kCount && !product[c] && __builtin_popcount(N.t_isect) == 1 && N.t_diff == 0 &&
+                 N.base < 0 && N.lo == 0 && N.hi == 0 && N.label < 0 && N.av_count == 0 && N.anchor_level < 0 &&
+                 !(N.isect >> x & 1u) && !(N.diff >> x & 1u) && (N.excl_in >> x & 1u);
+        }
+        if (ok) E.flags |= kIndepCounts;
+    }
+}
+
 // Share groups.  Children of an edge root at level 2 that apply the same set
 // operation (true-edge rows, anti-edge rows, exclusions) and differ only in
 // their id ranges -- count nodes, and enumeration nodes whose children only
@@ -868,6 +888,7 @@ void share_groups(Trie &T, const std::vector<bool> &product) {
             if (mem.size() < 2) continue;
             Node L = T.nodes[mem[0]];
             L.kind = kEnum;
+            L.flags = 0;
             L.group = 1;
             L.plan = 0;
             L.mult = 1;
@@ -1022,6 +1043,7 @@ Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit) {
         if (!emit) {
             std::vector<bool> product(T.nodes.size(), false);
             for (size_t i = 0; i < order2.size(); i++) product[i] = H[order2[i]].product;
+            mark_independent_counts(T, product);
             share_groups(T, product);
         }
     }
