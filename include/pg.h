@@ -206,7 +206,16 @@ typedef struct {
                               up to 64 parents in one flattened pass while those parents
                               average at most this many candidates, else parent by parent;
                               0 = always flattened */
-    int32_t reserved[2];   /* must be zero */
+    int32_t task_begin;    /* count over root tasks [task_begin, task_end) of the launch only
+                              (pg_launch_tasks gives their number): every match is found from
+                              exactly one root task (Sec. 5.1: matches grow from a start vertex),
+                              so counts over windows that partition the tasks sum to the full
+                              counts; tasks come costliest first.  0, 0 = every task */
+    int32_t task_end;      /* 0 = to the last task */
+    int32_t scan_max_degree; /* membership in a row of at most this degree (<= 32) is tested by
+                                scanning it (independent loads) instead of a binary search;
+                                0 = library default, -1 = never */
+    int32_t reserved;      /* must be zero */
 } pg_run_config;
 
 #define PG_RUN_COUNT_BYTES 1  /* also count the merge-model bytes of every set operation */
@@ -226,6 +235,9 @@ typedef struct {
     uint64_t root_tasks;     /* root tasks processed */
     int32_t grid_waves;
     int32_t chunk;
+    uint64_t tasks_started;  /* root tasks of the window in claims the wavefronts made: all of
+                                them after a complete run, the part reached before the stop
+                                when a time limit ended the run */
 } pg_run_stats;
 
 /* Count the matches of each plan (Sec. 3.2: count() is match() with a
@@ -290,6 +302,11 @@ pg_status pg_match_ex(pg_graph *g, const pg_plan *plan, pg_match_cb cb, void *us
  * have two vertices or more, then the vertices when some core has one; the
  * edges come costliest first. */
 pg_status pg_root_tasks(pg_graph *g, const pg_plan *plan, int64_t *n_tasks);
+
+/* Root tasks of one counting launch of these plans (the edges when some
+ * plan's cores have two vertices or more, then the vertices when some core
+ * has one): the range of pg_run_config.task_begin / task_end. */
+pg_status pg_launch_tasks(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, int64_t *n_tasks);
 
 /* pg_enumerate over the root tasks [task_begin, task_end) only (0 <=
  * task_begin < task_end <= pg_root_tasks). */

@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libpg.so")
 ROWBENCH = os.path.join(HERE, "librowbench.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["api.cpp", "plan.cpp", "engine.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "ingest.cpp", "engine.hip"]
 HEADERS = ["pg_internal.hpp", "engine.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

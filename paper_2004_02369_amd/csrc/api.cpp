@@ -72,6 +72,7 @@ struct pg_job {
     std::chrono::steady_clock::time_point t_submit;
     bool enqueued = false;  // work is on the stream that reads L.image
     int ctl_slot = -1;      // this job's block of the graph's pinned control blocks
+    long long tasks = 0;    // root tasks of its window
     ~pg_job();
 };
 
@@ -159,6 +160,10 @@ inline pg_job::~pg_job() {
 namespace {
 
 constexpr int64_t kHubMinDegree = 16;
+// rows of at most this degree may be scanned for membership; col carries
+// this many padding entries so a scan may read past a row's end
+constexpr int32_t kScanMaxDegree = 32;
+constexpr int32_t kScanDefault = 0;
 constexpr long long kArenaInts = 32768;  // per wavefront
 constexpr int64_t kHubBudgetBytes = int64_t(1) << 30;
 // label-sorted row copy: at most this many label offsets (4 bytes each)
@@ -198,30 +203,6 @@ pg_status upload(T **dst, const std::vector<T> &src, int64_t *bytes) {
     return PG_OK;
 }
 
-// LSD radix sort of 64-bit keys, 16 bits per pass.
-void radix_sort_u64(std::vector<uint64_t> &a, int key_bits) {
-    std::vector<uint64_t> tmp(a.size());
-    std::vector<size_t> cnt(1 << 16);
-    for (int shift = 0; shift < key_bits; shift += 16) {
-        std::fill(cnt.begin(), cnt.end(), 0);
-        for (uint64_t x : a) cnt[(x >> shift) & 0xFFFF]++;
-        size_t s = 0;
-        for (auto &c : cnt) {
-            size_t t = c;
-            c = s;
-            s += t;
-        }
-        for (uint64_t x : a) tmp[cnt[(x >> shift) & 0xFFFF]++] = x;
-        a.swap(tmp);
-    }
-}
-
-int bits_for(uint64_t v) {
-    int b = 0;
-    while (b < 64 && (v >> b)) b++;
-    return b;
-}
-
 }  // namespace
 
 extern "C" {
@@ -254,91 +235,20 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         if (dev >= ndev) { set_error("device out of range"); return PG_EINVAL; }
         DeviceGuard guard(dev);
 
-        // 1. canonical undirected simple edge set (Sec. 2.1)
-        std::vector<uint64_t> keys;
-        keys.reserve((size_t)m);
-        for (int64_t i = 0; i < m; i++) {
-            int32_t a = src[i], b = dst[i];
-            if (a < 0 || b < 0 || a >= n || b >= n) {
-                set_error("edge endpoint out of range at index " + std::to_string(i));
-                return PG_EINVAL;
-            }
-            if (a == b) continue;
-            if (a > b) std::swap(a, b);
-            keys.push_back((uint64_t)(uint32_t)a << 32 | (uint32_t)b);
-        }
-        radix_sort_u64(keys, 32 + bits_for((uint64_t)n));
-        keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-        const int64_t mu = (int64_t)keys.size();
-        if (2 * mu > (int64_t)INT32_MAX) {
-            set_error("graph too large: more than 2^31 - 1 adjacency entries");
-            return PG_EUNSUPPORTED;
-        }
-
-        // 2. degree order: rank by (degree, original id) ascending (Sec. 5.2)
-        std::vector<int64_t> deg(n, 0);
-        for (uint64_t k : keys) {
-            deg[k >> 32]++;
-            deg[k & 0xFFFFFFFFu]++;
-        }
-        int64_t dmax = 0;
-        for (int64_t d : deg) dmax = std::max(dmax, d);
-        if (dmax > INT32_MAX / 2) { set_error("degree too large"); return PG_EUNSUPPORTED; }
-        std::vector<int64_t> dstart(dmax + 2, 0);
-        for (int64_t d : deg) dstart[d + 1]++;
-        for (int64_t d = 0; d <= dmax; d++) dstart[d + 1] += dstart[d];
-        std::vector<int32_t> rank(n), perm(n);
-        for (int32_t v = 0; v < n; v++) {
-            int32_t r = (int32_t)dstart[deg[v]]++;
-            rank[v] = r;
-            perm[r] = v;
-        }
-
-        // 3. CSR in rank ids, rows sorted ascending
-        std::vector<int64_t> rp(n + 1, 0);
-        for (int32_t r = 0; r < n; r++) rp[r + 1] = rp[r] + deg[perm[r]];
-        std::vector<int32_t> col((size_t)(2 * mu));
+        // host part of ingest: canonical edges, degree order, CSR, tasks
+        pg::HostGraph h;
         {
-            std::vector<int64_t> fill(rp.begin(), rp.end() - 1);
-            for (uint64_t k : keys) {
-                int32_t a = rank[k >> 32], b = rank[k & 0xFFFFFFFFu];
-                col[fill[a]++] = b;
-                col[fill[b]++] = a;
+            std::string err;
+            const pg_status ist = pg::ingest(n, m, src, dst, labels, &h, &err);
+            if (ist) {
+                set_error(err);
+                return ist;
             }
         }
-        keys.clear();
-        keys.shrink_to_fit();
-        for (int32_t r = 0; r < n; r++) std::sort(col.begin() + rp[r], col.begin() + rp[r + 1]);
-        // split of each row into lower and upper neighbours (degree-oriented part)
-        std::vector<int32_t> up(n);
-        for (int32_t r = 0; r < n; r++)
-            up[r] = (int32_t)(std::lower_bound(col.begin() + rp[r], col.begin() + rp[r + 1], r) - (col.begin() + rp[r]));
-
-        // 4. root edge tasks u < v, costliest first (Sec. 5.2: start with the
-        //    highest-degree vertices); cost estimate d(u) + d(v)
-        std::vector<int32_t> tsrc((size_t)mu), tdst((size_t)mu);
-        {
-            std::vector<int64_t> cstart(2 * dmax + 3, 0);
-            for (int32_t u = 0; u < n; u++)
-                for (int64_t e = rp[u]; e < rp[u + 1]; e++)
-                    if (col[e] > u) cstart[2 * dmax - (deg[perm[u]] + deg[perm[col[e]]]) + 1]++;
-            for (size_t i = 1; i < cstart.size(); i++) cstart[i] += cstart[i - 1];
-            for (int32_t u = 0; u < n; u++)
-                for (int64_t e = rp[u]; e < rp[u + 1]; e++)
-                    if (col[e] > u) {
-                        int64_t slot = cstart[2 * dmax - (deg[perm[u]] + deg[perm[col[e]]])]++;
-                        tsrc[slot] = u;
-                        tdst[slot] = col[e];
-                    }
-        }
-        std::vector<int16_t> lab;
-        if (labels) {
-            lab.resize(n);
-            for (int32_t v = 0; v < n; v++) {
-                if (labels[v] < 0) { set_error("labels must be >= 0"); return PG_EINVAL; }
-                lab[rank[v]] = labels[v];
-            }
-        }
+        const int64_t mu = h.m, dmax = h.d_max;
+        std::vector<int64_t> &rp = h.rp;
+        std::vector<int32_t> &col = h.col, &up = h.up, &perm = h.perm, &tsrc = h.tsrc, &tdst = h.tdst;
+        std::vector<int16_t> &lab = h.lab;
 
         std::unique_ptr<pg_graph> g(new pg_graph());
         g->n = n;
@@ -367,7 +277,7 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         }
         if (n_labels > 0) {
             const int32_t stride = n_labels + 1;
-            std::vector<int32_t> ext((size_t)(4 * mu));
+            std::vector<int32_t> ext((size_t)(4 * mu) + kScanMaxDegree, INT32_MAX);
             std::copy(col.begin(), col.end(), ext.begin());
             std::vector<int32_t> off((size_t)n * (size_t)stride, 0);
             for (int32_t r = 0; r < n; r++) {
@@ -382,8 +292,11 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
             if ((st = upload(&g->col, ext, &g->device_bytes))) return st;
             if ((st = upload(&g->lab_off, off, &g->device_bytes))) return st;
             g->n_labels = n_labels;
-        } else if ((st = upload(&g->col, col, &g->device_bytes))) {
-            return st;
+        } else {
+            col.resize(col.size() + kScanMaxDegree, INT32_MAX);  // scans may read past a row's end
+            st = upload(&g->col, col, &g->device_bytes);
+            col.resize(col.size() - kScanMaxDegree);
+            if (st) return st;
         }
         if ((st = upload(&g->up, up, &g->device_bytes))) return st;
         // hub rows also as dense bitmaps: the highest-degree vertices (rank
@@ -552,8 +465,15 @@ pg_status check_args(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, 
             set_error("negative launch knob");
             return PG_EINVAL;
         }
-        for (int i = 0; i < 2; i++)
-            if (cfg->reserved[i]) { set_error("pg_run_config.reserved must be zero"); return PG_EINVAL; }
+        if (cfg->task_begin < 0 || cfg->task_end < 0 || (cfg->task_end > 0 && cfg->task_end <= cfg->task_begin)) {
+            set_error("bad root-task window");
+            return PG_EINVAL;
+        }
+        if (cfg->scan_max_degree < -1 || cfg->scan_max_degree > kScanMaxDegree) {
+            set_error("scan_max_degree must be in [-1, 32]");
+            return PG_EINVAL;
+        }
+        if (cfg->reserved) { set_error("pg_run_config.reserved must be zero"); return PG_EINVAL; }
     }
     return PG_OK;
 }
@@ -618,6 +538,56 @@ pg_status check_trie(const pg::Trie &T) {
     return PG_OK;
 }
 
+// Claims grow from 1 task to `chunk` over a window's costliest tasks: claim
+// j holds 1 + j / ramp tasks (at most chunk), and the growth spans the
+// window when ramp = 2 span / (chunk (chunk - 1)).
+long long chunk_ramp(long long span, int chunk) {
+    const long long c = std::max(1, chunk);
+    return c > 1 ? std::max(1ll, 2 * span / (c * (c - 1))) : 1;
+}
+
+// tasks covered by the first i claims (the kernel's claim_start)
+long long claim_start_host(long long i, int chunk, long long ramp) {
+    const long long full = ramp * (long long)(chunk - 1);
+    if (i <= full) {
+        const long long q = i / ramp, r = i - q * ramp;
+        return i + ramp * (q * (q - 1) / 2) + r * q;
+    }
+    const long long q = chunk - 1;
+    return full + ramp * (q * (q - 1) / 2) + (i - full) * (long long)chunk;
+}
+
+// The effective root-task window of a launch: the call's own (enumeration
+// windows) if set, else the run configuration's; end 0 = every task.
+void effective_window(const LaunchPlan &L, const LaunchArgs &la, const pg_run_config *cfg, long long *b, long long *e) {
+    *b = 0;
+    *e = 0;
+    if (la.task_begin || la.task_end) {
+        *b = la.task_begin;
+        *e = la.task_end;
+    } else if (cfg) {
+        *b = cfg->task_begin;
+        *e = cfg->task_end;
+    }
+    if (*e == 0) *e = L.n_et + L.n_vt;
+}
+
+long long window_tasks(const LaunchPlan &L, const LaunchArgs &la, const pg_run_config *cfg) {
+    long long b, e;
+    effective_window(L, la, cfg, &b, &e);
+    return e > b ? e - b : 0;
+}
+
+pg_status check_window(const LaunchPlan &L, const LaunchArgs &la, const pg_run_config *cfg) {
+    long long b, e;
+    effective_window(L, la, cfg, &b, &e);
+    if (b < 0 || e > L.n_et + L.n_vt || (e <= b && L.n_et + L.n_vt > 0)) {
+        set_error("bad root-task window (the launch has " + std::to_string(L.n_et + L.n_vt) + " root tasks)");
+        return PG_EINVAL;
+    }
+    return PG_OK;
+}
+
 pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev, unsigned long long *ctl,
                    int32_t *scratch, const LaunchArgs &la, int32_t n_plans, const pg_run_config *cfg) {
     pg::KParams P;
@@ -667,22 +637,24 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.n = g->n;
     P.n_roots = (int32_t)L.trie.roots.size();
     P.chunk = L.chunk;
-    {
-        // claims grow from 1 task to `chunk` over the window's costliest
-        // tasks: claim j holds 1 + j / ramp tasks, and the growth spans the
-        // window when ramp = 2 span / (chunk (chunk - 1))
-        const long long span = la.task_end > 0 ? la.task_end - la.task_begin : L.n_et + L.n_vt;
-        const long long c = std::max(1, L.chunk);
-        P.chunk_ramp = c > 1 ? std::max(1ll, 2 * span / (c * (c - 1))) : 1;
+    // this launch's root-task window: the call's own (enumeration windows),
+    // else the run configuration's
+    if (la.task_begin || la.task_end) {
+        P.task_begin = la.task_begin;
+        P.task_end = la.task_end;
+    } else if (cfg) {
+        P.task_begin = cfg->task_begin;
+        P.task_end = cfg->task_end;
     }
+    P.chunk_ramp = chunk_ramp((P.task_end > 0 ? P.task_end : L.n_et + L.n_vt) - P.task_begin, L.chunk);
     P.n_plans = n_plans;
     P.mode = la.mode;
     P.run_flags = cfg ? cfg->flags : 0;
     P.batch_max_avg = cfg ? cfg->batch_max_avg : 0;
+    P.scan_max = !cfg || cfg->scan_max_degree == 0 ? kScanDefault : std::max(0, cfg->scan_max_degree);
     P.mark = la.mark_dev;
     P.mark_words = la.mark_words;
-    P.task_begin = la.task_begin;
-    P.task_end = la.task_end;
+
     return P;
 }
 
@@ -730,11 +702,7 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     }
     LaunchPlan &L = g->launch;
     shape(g, cfg, L, la.mode, la.sizes != nullptr);  // the knobs may differ between calls
-    if (la.task_begin < 0 || la.task_end < 0 || (la.task_end > 0 && la.task_end <= la.task_begin) ||
-        la.task_end > L.n_et + L.n_vt || (la.task_end == 0 && la.task_begin > 0)) {
-        set_error("bad root-task window");
-        return PG_EINVAL;
-    }
+    if ((st = check_window(L, la, cfg))) return st;
 
     if (L.image.size() > g->trie_bytes) {
         dfree(g->trie_buf);
@@ -819,9 +787,12 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
         stats->total_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
         stats->logical_bytes = ctl[kCtlBytes];
-        stats->root_tasks = la.task_end > 0 ? (uint64_t)(la.task_end - la.task_begin) : (uint64_t)(L.n_et + L.n_vt);
+        const long long wt = window_tasks(L, la, cfg);
+        stats->root_tasks = (uint64_t)wt;
         stats->grid_waves = L.grid;
         stats->chunk = L.chunk;
+        stats->tasks_started =
+            (uint64_t)std::min(wt, claim_start_host((long long)ctl[kCtlCursor], L.chunk, chunk_ramp(wt, L.chunk)));
     }
     return read_ctl(ctl, n_plans, counts, emitted);
 }
@@ -864,6 +835,7 @@ pg_status pg_count_noalloc(pg_graph *g, const pg_plan *const *plans, int32_t n_p
         L.trie = pg::build_trie(impls, false);
         if ((st = check_trie(L.trie))) return st;
         shape(g, cfg, L, pg::kModeCount, false);
+        if ((st = check_window(L, LaunchArgs{}, cfg))) return st;
         void *base = nullptr;
         size_t cap = 0;
         PG_HIP(pg::static_scratch(&base, &cap));
@@ -972,6 +944,22 @@ pg_status pg_root_tasks(pg_graph *g, const pg_plan *plan, int64_t *n_tasks) {
     try {
         std::vector<const pg::PlanImpl *> impls{&plan->impl};
         const pg::Trie T = pg::build_trie(impls, true);
+        *n_tasks = (T.has_edge_root ? g->m : 0) + (T.has_vertex_root ? (int64_t)g->n : 0);
+        return PG_OK;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return PG_ENOMEM;
+    }
+}
+
+pg_status pg_launch_tasks(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, int64_t *n_tasks) {
+    if (!n_tasks) { set_error("n_tasks is NULL"); return PG_EINVAL; }
+    pg_status st = check_args(g, plans, n_plans, nullptr);
+    if (st) return st;
+    try {
+        std::vector<const pg::PlanImpl *> impls;
+        for (int i = 0; i < n_plans; i++) impls.push_back(&plans[i]->impl);
+        const pg::Trie T = pg::build_trie(impls, false);
         *n_tasks = (T.has_edge_root ? g->m : 0) + (T.has_vertex_root ? (int64_t)g->n : 0);
         return PG_OK;
     } catch (const std::bad_alloc &) {
@@ -1094,7 +1082,7 @@ static pg_status prepare_job(pg_graph *g, const pg_plan *const *plans, int32_t n
     if (cfg) c = *cfg;
     if (mode == PG_JOB_EXISTS && !c.chunk) c.chunk = 1;  // poll the stop flag often
     shape(g, &c, *L, mode == PG_JOB_EXISTS ? pg::kModeExists : pg::kModeCount, false);
-    return PG_OK;
+    return check_window(*L, LaunchArgs{}, cfg);
 }
 
 pg_status pg_job_workspace_size(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, int32_t mode,
@@ -1150,6 +1138,7 @@ pg_status pg_submit(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, i
         }
         j->n_plans = n_plans;
         j->mode = mode;
+        j->tasks = window_tasks(j->L, LaunchArgs{}, cfg);
         j->s = reinterpret_cast<hipStream_t>(hip_stream);
         j->t_submit = std::chrono::steady_clock::now();
         char *base = static_cast<char *>(workspace);
@@ -1210,9 +1199,11 @@ pg_status pg_job_finish(pg_job *j, uint64_t *counts, pg_run_stats *stats) {
         stats->total_ms =
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - j->t_submit).count();
         stats->logical_bytes = ctl[kCtlBytes];
-        stats->root_tasks = (uint64_t)(j->L.n_et + j->L.n_vt);
+        stats->root_tasks = (uint64_t)j->tasks;
         stats->grid_waves = j->L.grid;
         stats->chunk = j->L.chunk;
+        stats->tasks_started = (uint64_t)std::min(
+            j->tasks, claim_start_host((long long)ctl[kCtlCursor], j->L.chunk, chunk_ramp(j->tasks, j->L.chunk)));
     }
     if (j->mode == PG_JOB_EXISTS) {
         // partial sums of an early-stopped search may wrap; only > 0 matters

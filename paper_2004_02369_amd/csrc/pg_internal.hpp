@@ -130,6 +130,23 @@ struct Trie {
 
 Trie build_trie(const std::vector<const PlanImpl *> &plans, bool emit);
 
+// A graph after the host part of ingest, in rank ids (degree order).
+struct HostGraph {
+    int32_t n = 0;
+    int64_t m = 0;                // distinct undirected edges
+    int32_t d_max = 0;
+    std::vector<int64_t> rp;      // n + 1 row offsets
+    std::vector<int32_t> col;     // 2m entries, each row ascending
+    std::vector<int32_t> up;      // per row: index of its first neighbour above it
+    std::vector<int32_t> perm;    // rank -> original id
+    std::vector<int32_t> tsrc, tdst;  // oriented edges u < v, costliest first
+    std::vector<int16_t> lab;     // labels in rank order (empty: unlabelled)
+};
+
+// Host part of pg_load_graph (see ingest.cpp); *err describes a failure.
+pg_status ingest(int32_t n, int64_t m, const int32_t *src, const int32_t *dst, const int16_t *labels,
+                 HostGraph *out, std::string *err);
+
 // Plan compiler entry (host only).
 pg_status compile_plan(const pg_pattern_desc *desc, const pg_plan_options *opt, PlanImpl *out,
                        std::string *err);

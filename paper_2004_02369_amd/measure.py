@@ -116,26 +116,41 @@ def c1(args, pg, gg, pt):
 
 def c3(args, pg, gg, pt):
     """The 22-plan family (21 induced 5-motifs + K5) at full size: each plan
-    alone under a device time limit, then every plan that finished in one
-    launch (default and tuned knobs) against the sum of their single
-    launches.  Counts of a finished launch are exact; the batch must repeat
-    the singles' counts, and K5 must equal the induced K5 when both finish."""
+    alone under a device time limit: the exact count when it finishes, else
+    the share of root tasks reached, a linear projection of the full time
+    and the partial count.  Then the finishing plans batched against their
+    single launches, and the tuner on them.  K5 must equal the induced K5."""
     from . import tune
     t0 = time.perf_counter()
     G = pg.load_graph(*gg.workload(args.workload), device=0)
     _say(f"{args.workload}: n={G.n} m={G.m} d_max={G.d_max} ready in {time.perf_counter() - t0:.1f} s")
     specs = pt.all_vertex_induced(5) + [pt.clique(5)]
     plans = [pg.plan_pattern(s) for s in specs]
+    lo_plan, hi_plan = (int(x) for x in args.plans.split("-"))
     singles = []
     for i, p in enumerate(plans):
+        rec = {"plan": i, "edges": specs[i]["edges"], "core": p.info()["core"], "ms": None, "count": None}
+        if not (lo_plan <= i <= hi_plan):
+            continue
         try:
             c, st = pg.count_ex(G, [p], time_limit_ms=args.limit_ms)
-            singles.append({"plan": i, "edges": specs[i]["edges"], "ms": st["kernel_ms"], "count": c[0]})
+            rec.update(ms=st["kernel_ms"], count=c[0], root_tasks=st["root_tasks"])
         except pg.PGError as e:
             if e.status != pg.PG_ETIMEDOUT:
                 raise
-            singles.append({"plan": i, "edges": specs[i]["edges"], "ms": None, "count": None})
-        _say(f"plan {i} {specs[i]['edges']}: {singles[-1]['ms']} ms, count {singles[-1]['count']}")
+            # stopped at the limit: the share of root tasks reached, a linear
+            # projection of the full time from it (tasks come roughly
+            # costliest first by d(u) + d(v), but a plan's cost per task need
+            # not follow that order, so this is an estimate, not a bound), and
+            # the partial count (a lower bound)
+            st = e.stats
+            frac = st["tasks_started"] / max(1, st["root_tasks"])
+            rec.update(stopped="ETIMEDOUT", kernel_ms_at_stop=st["kernel_ms"], root_tasks=st["root_tasks"],
+                       tasks_started=st["tasks_started"], fraction_started=frac,
+                       projected_ms=st["kernel_ms"] / frac if frac > 0 else None, count_lower_bound=e.counts[0])
+        singles.append(rec)
+        _say(f"plan {i} {specs[i]['edges']}: " + json.dumps({k: v for k, v in rec.items() if k not in ("edges",)}))
+    singles = [r for r in singles if "root_tasks" in r]
     done = [r for r in singles if r["ms"] is not None]
     batch = [plans[r["plan"]] for r in done]
     out = {"measure": "c3", "workload": args.workload, "n": G.n, "m": G.m, "d_max": G.d_max,
@@ -147,11 +162,14 @@ def c3(args, pg, gg, pt):
         out["singles_sum_ms"] = sum(r["ms"] for r in done)
         out["batched_speedup"] = out["singles_sum_ms"] / st["kernel_ms"]
         _say(f"batch of {len(done)}: {st['kernel_ms']:.1f} ms vs {out['singles_sum_ms']:.1f} ms one launch each")
-        tuned = tune.autotune(G, batch, budget_s=args.tune_budget, log=_say)
-        out["tuned"] = {"knobs": tuned["knobs"], "ms": tuned["ms"], "default_ms": tuned["default_ms"],
-                        "trials": len(tuned["trials"])}
-    if singles[-1]["count"] is not None and singles[-2]["count"] is not None:
-        assert singles[-1]["count"] == singles[-2]["count"], "K5 differs from the induced K5"
+        if args.tune_budget > 0:
+            tuned = tune.autotune(G, batch, budget_s=args.tune_budget, log=_say)
+            out["tuned"] = {"knobs": tuned["knobs"], "ms": tuned["ms"], "default_ms": tuned["default_ms"],
+                            "trials": len(tuned["trials"])}
+    byplan = {r["plan"]: r for r in singles}
+    k5, ik5 = byplan.get(len(specs) - 1), byplan.get(len(specs) - 2)
+    if k5 and ik5 and k5["count"] is not None and ik5["count"] is not None:
+        assert k5["count"] == ik5["count"], "K5 differs from the induced K5"
         out["k5_equals_induced_k5"] = True
     print(json.dumps(out), flush=True)
 
@@ -310,6 +328,7 @@ def main(argv=None):
     ap.add_argument("--pairs", type=int, default=2_000_000)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--budgets", default="1024,4096,16384,32768")
+    ap.add_argument("--plans", default="0-21", help="c3: the plans to run (a-b, of the 22)")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--limit-ms", type=int, default=600000)
     ap.add_argument("--tune-budget", type=float, default=60.0)

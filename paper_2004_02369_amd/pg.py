@@ -75,20 +75,21 @@ class pg_plan_info_t(ctypes.Structure):
 class pg_run_config(ctypes.Structure):
     _fields_ = [("grid_waves", ctypes.c_int32), ("chunk", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("time_limit_ms", ctypes.c_int32), ("hub_min_degree", ctypes.c_int32),
-                ("batch_max_avg", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("batch_max_avg", ctypes.c_int32), ("task_begin", ctypes.c_int32), ("task_end", ctypes.c_int32),
+                ("scan_max_degree", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class pg_run_stats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("logical_bytes", ctypes.c_uint64), ("root_tasks", ctypes.c_uint64),
-                ("grid_waves", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+                ("grid_waves", ctypes.c_int32), ("chunk", ctypes.c_int32), ("tasks_started", ctypes.c_uint64)]
 
 
 MATCH_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_void_p)
 
 EXPORTS = ["pg_load_graph", "pg_graph_info", "pg_graph_csr", "pg_free_graph", "pg_plan_pattern",
            "pg_plan_pattern_ex", "pg_plan_info", "pg_free_plan", "pg_plan_programs", "pg_count", "pg_count_ex",
-           "pg_count_noalloc", "pg_exists", "pg_enumerate", "pg_match", "pg_match_ex", "pg_root_tasks", "pg_enumerate_range",
+           "pg_count_noalloc", "pg_exists", "pg_enumerate", "pg_match", "pg_match_ex", "pg_root_tasks", "pg_launch_tasks", "pg_enumerate_range",
            "pg_domain_sizes", "pg_job_workspace_size", "pg_submit", "pg_job_poll", "pg_job_finish",
            "pg_last_error"]
 
@@ -125,6 +126,7 @@ def lib():
     L.pg_match.argtypes = [vp, vp, MATCH_CB, vp, ctypes.POINTER(u64)]
     L.pg_match_ex.argtypes = [vp, vp, MATCH_CB, vp, ctypes.POINTER(u64), u64]
     L.pg_root_tasks.argtypes = [vp, vp, ctypes.POINTER(i64)]
+    L.pg_launch_tasks.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(i64)]
     L.pg_enumerate_range.argtypes = [vp, vp, i64, i64, vp, u64, ctypes.POINTER(u64), vp]
     L.pg_domain_sizes.argtypes = [vp, ctypes.POINTER(vp), i32, ctypes.POINTER(u64), ctypes.POINTER(pg_run_config), vp]
     L.pg_job_workspace_size.argtypes = [vp, ctypes.POINTER(vp), i32, i32, ctypes.POINTER(pg_run_config),
@@ -298,7 +300,8 @@ def plan_pattern(spec, mode: int = PG_PLAN_AUTO, anchor: int | None = None) -> P
 
 # --------------------------------------------------------------- counting
 
-RUN_KNOBS = ("grid_waves", "chunk", "flags", "time_limit_ms", "hub_min_degree", "batch_max_avg")
+RUN_KNOBS = ("grid_waves", "chunk", "flags", "time_limit_ms", "hub_min_degree", "batch_max_avg", "task_begin",
+             "task_end", "scan_max_degree")
 
 
 def run_config(**kw) -> pg_run_config:
@@ -318,8 +321,14 @@ def count_ex(graph: Graph, plans, stream=None, **knobs):
     out = (ctypes.c_uint64 * len(plans))()
     cfg = run_config(**knobs)
     st = pg_run_stats()
-    _check(lib().pg_count_ex(graph._h, arr, len(plans), out, ctypes.byref(cfg), ctypes.byref(st),
-                             _stream_ptr(stream)))
+    rc = lib().pg_count_ex(graph._h, arr, len(plans), out, ctypes.byref(cfg), ctypes.byref(st), _stream_ptr(stream))
+    if rc < 0:
+        err = PGError(rc, lib().pg_last_error().decode())
+        # a run stopped by its time limit: the counts so far (lower bounds)
+        # and how far it got
+        err.counts = [int(x) for x in out]
+        err.stats = _stats(st)
+        raise err
     return [int(x) for x in out], _stats(st)
 
 
@@ -336,7 +345,8 @@ def count_noalloc(graph: Graph, plans, stream=None, **knobs):
 
 def _stats(st):
     return {"kernel_ms": st.kernel_ms, "total_ms": st.total_ms, "logical_bytes": st.logical_bytes,
-            "root_tasks": st.root_tasks, "grid_waves": st.grid_waves, "chunk": st.chunk}
+            "root_tasks": st.root_tasks, "grid_waves": st.grid_waves, "chunk": st.chunk,
+            "tasks_started": st.tasks_started}
 
 
 def count(graph: Graph, plans, stream=None, **kw):
@@ -380,6 +390,15 @@ def enumerate_matches(graph: Graph, plan: Plan, cap: int | None = None, stream=N
 def root_tasks(graph: Graph, plan: Plan) -> int:
     n = ctypes.c_int64()
     _check(lib().pg_root_tasks(graph._h, plan._h, ctypes.byref(n)))
+    return int(n.value)
+
+
+def launch_tasks(graph: Graph, plans) -> int:
+    """Root tasks of one counting launch of these plans (pg_launch_tasks)."""
+    plans = list(plans)
+    arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
+    n = ctypes.c_int64()
+    _check(lib().pg_launch_tasks(graph._h, arr, len(plans), ctypes.byref(n)))
     return int(n.value)
 
 

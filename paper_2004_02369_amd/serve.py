@@ -128,6 +128,12 @@ class Batch:
     t_submit: float = 0.0
     heavy: bool = False
     lid: int = -1
+    # a heavy count launch runs as consecutive root-task windows: those still
+    # to run, the counts and kernel time of the windows done so far
+    windows: list = field(default_factory=list)
+    acc: list = None
+    kernel_ms: float = 0.0
+    waiting: bool = False       # between two windows: holds its workspace and one slot
 
 
 def _merge(requests):
@@ -172,6 +178,21 @@ class Policy:
         else:
             for p in plans:
                 self.est.setdefault(id(p), ms / len(plans))
+
+
+class _Failed:
+    """Stands in for the job of a windowed launch whose next window could not
+    start: done at once, finish() raises the error."""
+
+    def __init__(self, msg):
+        self.msg = msg
+
+    def done(self):
+        return True
+
+    def finish(self):
+        from . import pg
+        raise pg.PGError(pg.PG_EDEVICE, self.msg)
 
 
 def next_batch(queue, size_of, pool: Pool, policy: Policy | None = None, allow_heavy: bool = True):
@@ -230,6 +251,23 @@ def next_batch(queue, size_of, pool: Pool, policy: Policy | None = None, allow_h
         chosen.pop()
 
 
+def task_windows(total: int, n: int) -> list[tuple[int, int]]:
+    """Cut root tasks [0, total) into at most n consecutive windows that
+    partition them.  Tasks come costliest first, so the windows grow
+    geometrically (each twice the one before) and their costs are closer to
+    equal than equal task counts would give."""
+    n = max(1, min(n, total))
+    if n == 1 or total <= 1:
+        return [(0, total)]
+    unit = total / (2 ** n - 1)
+    cuts = [0] + [min(total, max(1, round(unit * (2 ** (i + 1) - 1)))) for i in range(n - 1)] + [total]
+    out = []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        if b > a:
+            out.append((a, b))
+    return out
+
+
 # ----------------------------------------------------------------- server
 
 _STREAMS = {}
@@ -265,7 +303,7 @@ class Server:
     docstring).  Drive it with offer() and pump()."""
 
     def __init__(self, graph, pool_bytes: int, slots: int | None = None, time_limit_ms: int = 0,
-                 policy: Policy | None = None):
+                 policy: Policy | None = None, window_ms: float = 0.0):
         import torch
         from . import pg
         self.pg = pg
@@ -295,6 +333,11 @@ class Server:
         self.launches = 0
         self.merged_requests = 0
         self.log = []  # one record per finished launch
+        # heavy count launches are cut into root-task windows of about this
+        # many ms each (by the policy's estimate); between two windows the
+        # launch gives back its extra slots, so light requests start there
+        self.window_ms = window_ms
+        self.windows_run = 0
 
     def launch_shape(self, plans, kind, heavy=False):
         """(workspace bytes, grid) of a launch: a heavy one is wide unless its
@@ -326,8 +369,8 @@ class Server:
         pg = self.pg
         progress = 0
         for b in list(self.inflight):
-            if b.job.done():
-                progress += self._retire(b)
+            if b.job is not None and b.job.done():
+                progress += self._advance(b) if b.windows else self._retire(b)
         while self.free_slots and self.queue:
             heavy_busy = any(x.heavy for x in self.inflight)
             allow_heavy = not heavy_busy and len(self.free_slots) >= self.heavy_width
@@ -357,9 +400,17 @@ class Server:
             ws = self.mem[b.offset:b.offset + b.nbytes]
             mode = pg.PG_JOB_EXISTS if b.kind == "exists" else pg.PG_JOB_COUNT
             b.t_submit = time.perf_counter()
+            win = {}
+            if b.heavy and b.kind == "count" and self.window_ms > 0:
+                n = int(math.ceil(self.policy.cost(b.plans) / max(1, len(b.extra_slots) + 1) / self.window_ms))
+                if n > 1:
+                    b.windows = task_windows(pg.launch_tasks(self.g, b.plans), min(n, 16))
+                    b.acc = [0] * len(b.plans)
+                    a, e = b.windows.pop(0)
+                    win = {"task_begin": a, "task_end": e}
             try:
                 b.job = pg.submit(self.g, b.plans, ws, self.streams[b.slot], mode=mode, grid_waves=b.grid,
-                                  time_limit_ms=self.time_limit_ms)
+                                  time_limit_ms=self.time_limit_ms, **win)
             except pg.PGError as e:
                 self._release(b)
                 for r in b.requests:
@@ -375,7 +426,51 @@ class Server:
             self.launches += 1
             self.merged_requests += len(b.requests) - 1
             progress += len(b.requests)
+        progress += self._resume()
         return progress
+
+    def _advance(self, b) -> int:
+        """A windowed launch finished one window: fold its counts in and give
+        back the extra slots until the next window starts (_resume)."""
+        try:
+            res, st = b.job.finish()
+        except self.pg.PGError as e:
+            b.windows = []
+            b.acc = None
+            b.job = _Failed(str(e))
+            return self._retire(b)
+        b.acc = [x + y for x, y in zip(b.acc, res)]
+        b.kernel_ms += st["kernel_ms"]
+        self.windows_run += 1
+        b.job = None
+        b.waiting = True
+        self.free_slots.extend(b.extra_slots)
+        b.extra_slots = []
+        return 1
+
+    def _resume(self) -> int:
+        """Start the next window of every waiting windowed launch, on its own
+        slot plus the free slots up to its width (fewer while light launches
+        hold them)."""
+        started = 0
+        for b in self.inflight:
+            if not b.waiting:
+                continue
+            while self.free_slots and len(b.extra_slots) < self.heavy_width - 1:
+                b.extra_slots.append(self.free_slots.pop())
+            grid = self.grid * (1 + len(b.extra_slots))
+            a, e = b.windows.pop(0)
+            ws = self.mem[b.offset:b.offset + b.nbytes]
+            try:
+                b.job = self.pg.submit(self.g, b.plans, ws, self.streams[b.slot], mode=self.pg.PG_JOB_COUNT,
+                                       grid_waves=min(grid, b.grid), time_limit_ms=self.time_limit_ms,
+                                       task_begin=a, task_end=e)
+            except self.pg.PGError as err:
+                b.windows = []
+                b.job = _Failed(str(err))
+            b.waiting = False
+            started += 1
+        return started
 
     def _release(self, b):
         self.pool.free(b.offset)
@@ -387,6 +482,9 @@ class Server:
         err, st = None, {}
         try:
             res, st = b.job.finish()
+            if b.acc is not None:
+                res = [x + y for x, y in zip(b.acc, res)]
+                st = dict(st, kernel_ms=b.kernel_ms + st["kernel_ms"])
             self.policy.observe(b.plans, st["kernel_ms"])
         except self.pg.PGError as e:
             err, res = str(e), None

@@ -200,6 +200,11 @@ def test_batched_equals_single_and_perturbations(pg, orc):
                                (100, 8, pg.PG_RUN_NO_TASK_BATCH | pg.PG_RUN_NO_MODE_B)]:
         say("perturbation", grid, chunk, flags)
         assert pg.count(Gd, plans, grid_waves=grid, chunk=chunk, flags=flags) == batched
+    # intersection variants per degree bucket: scans of short rows, binary
+    # search, bitmaps, in every mix
+    for scan, hub in [(4, 0), (8, 64), (16, -1), (32, 0), (32, -1), (-1, -1)]:
+        say("variants", scan, hub)
+        assert pg.count(Gd, plans, scan_max_degree=scan, hub_min_degree=hub) == batched
 
 
 def test_merge_model_bytes_deterministic(pg):
@@ -327,3 +332,40 @@ def test_share_groups_equal_oracle(pg, orc):
         assert pg.count(Gd, plans, grid_waves=grid, chunk=chunk, batch_max_avg=bma, flags=flags) == want
     # existence of a share-group member stops early and finds the same answer
     assert pg.exists(Gd, pg.plan_pattern(pt.EDGE_CORE_5["book3"])) is (want[specs.index(pt.EDGE_CORE_5["book3"])] > 0)
+
+
+def test_task_windows_partition_the_counts(pg, orc):
+    """Counts over root-task windows that partition a launch's tasks (edges
+    first, then vertices) sum to the full counts, through the synchronous
+    call and through jobs; windows outside the launch are refused."""
+    import torch
+    g = gg.chung_lu(2000, 14000, 2.1, 200.0, seed=9)
+    say("task windows, chung_lu 2000/14000")
+    Gd = G(pg, g)
+    specs = pt.all_vertex_induced(4) + [pt.clique(3), pt.star(3), pt.EDGE_CORE_5["cricket"]]
+    plans = [pg.plan_pattern(s) for s in specs]
+    og = orc.Graph.from_tuple(g)
+    want = [orc.count(og, s) for s in specs]
+    assert pg.count(Gd, plans) == want
+    T = pg.launch_tasks(Gd, plans)
+    assert T == Gd.m + Gd.n  # an edge-rooted and a vertex-rooted plan
+    rng = np.random.Generator(np.random.PCG64(3))
+    cuts = [0] + sorted(rng.choice(np.arange(1, T), 9, replace=False).tolist()) + [T]
+    total = [0] * len(specs)
+    s = torch.cuda.current_stream(0)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        c = pg.count(Gd, plans, task_begin=a, task_end=b)
+        nb = pg.job_workspace_size(Gd, plans, task_begin=a, task_end=b)
+        ws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda:0")
+        off = (-ws.data_ptr()) % 256
+        j, _ = pg.submit(Gd, plans, ws[off:off + nb], s, task_begin=a, task_end=b).finish()
+        assert j == c
+        total = [x + y for x, y in zip(total, c)]
+    assert total == want
+    assert pg.count(Gd, plans, task_begin=cuts[5]) == [x - y for x, y in zip(
+        want, [sum(col) for col in zip(*[pg.count(Gd, plans, task_begin=a, task_end=b)
+                                          for a, b in zip(cuts[:5], cuts[1:6])])])]
+    for a, b in ((5, 5), (0, T + 1), (T, 0)):
+        with pytest.raises(pg.PGError) as e:
+            pg.count(Gd, plans, task_begin=a, task_end=b)
+        assert e.value.status == pg.PG_EINVAL

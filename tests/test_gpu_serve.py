@@ -257,12 +257,18 @@ def test_served_results_equal_oracle(pg, orc):
         res, _, err = alone[q.name]
         assert err is None, (q.name, err)
         assert res == want[q.name], (q.name, res, want[q.name])
-    srv = serve.Server(G, 2 * biggest(3) + 4096, slots=3, time_limit_ms=120000,
-                       policy=serve.policy_from(queries, alone, 3, light_ms=5.0))
-    times, picks = serve.poisson_arrivals(2000.0, 400, len(queries), seed=12)
-    reqs, t0 = serve.run_open_loop(srv, queries, times, picks)
-    assert len(reqs) == 400 and srv.idle()
-    for r in reqs:
-        assert r.error is None, (r.query.name, r.error)
-        assert r.result == want[r.query.name], r.query.name
-    assert srv.merged_requests > 0
+    for window_ms in (0.0, 0.5):
+        # window_ms > 0: heavy launches run as root-task windows, light
+        # requests start between them
+        say(f"served mix, window_ms {window_ms}")
+        srv = serve.Server(G, 2 * biggest(3) + 4096, slots=3, time_limit_ms=120000,
+                           policy=serve.policy_from(queries, alone, 3, light_ms=2.0), window_ms=window_ms)
+        times, picks = serve.poisson_arrivals(2000.0, 400, len(queries), seed=12)
+        reqs, t0 = serve.run_open_loop(srv, queries, times, picks)
+        assert len(reqs) == 400 and srv.idle()
+        for r in reqs:
+            assert r.error is None, (r.query.name, r.error)
+            assert r.result == want[r.query.name], r.query.name
+        assert srv.merged_requests > 0
+        assert (srv.windows_run > 0) == (window_ms > 0)
+        assert srv.pool.used == 0 and sorted(srv.free_slots) == [0, 1, 2]

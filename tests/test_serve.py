@@ -214,3 +214,14 @@ def test_pattern_key_identifies_same_patterns():
     assert serve.pattern_key(k4) == serve.pattern_key(dict(k4, induced=True))
     assert serve.pattern_key(pt.star(4)) != serve.pattern_key(pt.star(4, induced=True))
     assert serve.pattern_key(pt.chain(3)) != serve.pattern_key(dict(pt.chain(3), labels=[0, 1, 0]))
+
+
+def test_task_windows_partition_and_grow():
+    for total, n in [(1, 5), (10, 1), (10, 3), (1000, 16), (67108864, 16), (5, 16), (2, 2)]:
+        w = serve.task_windows(total, n)
+        assert w[0][0] == 0 and w[-1][1] == total
+        assert all(a < b for a, b in w) and all(w[i][1] == w[i + 1][0] for i in range(len(w) - 1))
+        assert len(w) <= max(1, min(n, total))
+    w = serve.task_windows(1 << 20, 8)
+    sizes = [b - a for a, b in w]
+    assert len(w) == 8 and all(abs(sizes[i + 1] / sizes[i] - 2) < 0.01 for i in range(7))
