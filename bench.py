@@ -33,7 +33,7 @@ WORKLOAD = "rmat22_64m"
 C2_WORKLOAD = "chunglu_100k_1m"
 HBM_PEAK_GBPS = 8000.0
 # the batch: names in the serving catalogue (paper_2004_02369_amd.serve)
-BATCH = ["triangle", "wedge", "induced_wedge", "clique4", "book3", "cricket"]
+from paper_2004_02369_amd.serve import SERVING_BATCH as BATCH  # noqa: E402
 SERVE_EXTRA = ["clique6_exists", "clique8_exists", "clique10_exists", "clique12_exists", "clique14_exists"]
 
 
@@ -227,7 +227,18 @@ def main():
     queries = {q.name: q for q in serve.catalogue(pg, pt)}
     plans = [queries[n].plans[0] for n in BATCH]
     plan_ms = sum(p.info()["plan_ms"] for p in plans)
-    knobs = json.loads(args.knobs) if args.knobs else {}
+    # launch knobs: the committed tuning record for this graph and batch
+    # (paper_2004_02369_amd/tuned.json, written by `measure tune`), unless given
+    tuning = None
+    if args.knobs:
+        knobs = json.loads(args.knobs)
+    else:
+        from paper_2004_02369_amd import tune
+        rec = tune.lookup(G, plans, tune.RECORDS)
+        knobs = {k: v for k, v in (rec["knobs"] if rec else {}).items() if v}
+        if rec:
+            tuning = {"record": True, "default_kernel_ms": rec["default_ms"], "tuned_kernel_ms": rec["ms"],
+                      "trials": len(rec["trials"])}
 
     # merge-model bytes of one launch (a separate, untimed counting run)
     counts_b, st_b = pg.count_ex(G, plans, stream=stream, **dict(knobs, flags=knobs.get("flags", 0) | pg.PG_RUN_COUNT_BYTES))
@@ -268,6 +279,7 @@ def main():
                                + ", ".join(BATCH),
                    "n": G.n, "m": G.m, "d_max": G.d_max, "patterns": len(BATCH), "parallelism": "1 GPU"},
         "knobs": knobs,
+        "tuning": tuning,
         "counts": dict(zip(BATCH, counts)),
         "kernel_ms": avg_kernel_ms,
         "plan_ms": plan_ms,

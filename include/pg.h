@@ -224,6 +224,7 @@ typedef struct {
 #define PG_RUN_LIGHT_KERNEL 8   /* run a long counting launch on the four-waves-per-SIMD build of
                                    the kernel (128 VGPRs, no spills) instead of the five-wave one;
                                    shorter launches always use it */
+#define PG_RUN_WAVE_TIMES 32     /* record the first and last wavefront finish times (pg_run_stats) */
 #define PG_RUN_NO_SHARE 16      /* evaluate every level-2 node of an edge root on its own, without the
                                    share groups that read several nodes' candidates from one
                                    materialised set (Sec. 3.2: several patterns in one call) */
@@ -238,6 +239,9 @@ typedef struct {
     uint64_t tasks_started;  /* root tasks of the window in claims the wavefronts made: all of
                                 them after a complete run, the part reached before the stop
                                 when a time limit ended the run */
+    double wave_done_first_ms; /* with PG_RUN_WAVE_TIMES: when the first and the last wavefront */
+    double wave_done_last_ms;  /* finished, after the first one started (device clock); their
+                                  difference is the launch's load imbalance */
 } pg_run_stats;
 
 /* Count the matches of each plan (Sec. 3.2: count() is match() with a

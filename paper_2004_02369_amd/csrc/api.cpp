@@ -175,7 +175,9 @@ constexpr int kCtlEmit = 65;
 constexpr int kCtlBytes = 66;
 constexpr int kCtlFlags = 67;  // four int32 in two slots: overflow, stop, timed out, unused
 constexpr int kCtlStart = 69;  // device wall clock at the first wavefront's start
-constexpr int kCtlWords = 70;
+constexpr int kCtlDoneFirst = 70;  // wave finish times (PG_RUN_WAVE_TIMES): ~(earliest), latest, in ticks
+constexpr int kCtlDoneLast = 71;
+constexpr int kCtlWords = 72;
 constexpr int kJobSlots = 64;  // asynchronous jobs in flight per graph
 
 struct DeviceGuard {
@@ -626,6 +628,7 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.out = la.out;
     P.bytes_ctr = ctl + kCtlBytes;
     P.t_start = ctl + kCtlStart;
+    P.wave_done = ctl + kCtlDoneFirst;
     P.time_budget = cfg && cfg->time_limit_ms ? (long long)cfg->time_limit_ms * g->wall_khz : 0;
     P.scratch = L.enum_levels ? scratch : nullptr;
     P.wave_stride = (long long)L.enum_levels * L.set_cap + L.arena_cap;
@@ -793,6 +796,10 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
         stats->chunk = L.chunk;
         stats->tasks_started =
             (uint64_t)std::min(wt, claim_start_host((long long)ctl[kCtlCursor], L.chunk, chunk_ramp(wt, L.chunk)));
+        if (cfg && (cfg->flags & PG_RUN_WAVE_TIMES)) {
+            stats->wave_done_first_ms = (double)(~ctl[kCtlDoneFirst]) / (double)g->wall_khz;
+            stats->wave_done_last_ms = (double)ctl[kCtlDoneLast] / (double)g->wall_khz;
+        }
     }
     return read_ctl(ctl, n_plans, counts, emitted);
 }

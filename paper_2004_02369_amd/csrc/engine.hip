@@ -1445,7 +1445,7 @@ __device__ __forceinline__ void match_body(const KParams P) {
         L.stop = 0;
         L.bytes = 0;
         L.t_start = 0;
-        if (P.time_budget) {
+        if (P.time_budget || (P.run_flags & PG_RUN_WAVE_TIMES)) {
             const unsigned long long now = wall_clock64();
             const unsigned long long old = atomicCAS(P.t_start, 0ull, now);
             L.t_start = old ? old : now;
@@ -1594,6 +1594,13 @@ __device__ __forceinline__ void match_body(const KParams P) {
         if (old + C.acc < old) atomicOr(P.flags, 1);
     }
     if (lane == 0 && L.bytes) atomicAdd(P.bytes_ctr, L.bytes);
+    // load balance: when this wavefront ran out of tasks, after the first
+    // wavefront's start (the earliest is kept complemented, so a max finds it)
+    if ((P.run_flags & PG_RUN_WAVE_TIMES) && lane == 0) {
+        const unsigned long long t = wall_clock64() - L.t_start;
+        atomicMax(P.wave_done, ~t);
+        atomicMax(P.wave_done + 1, t);
+    }
 }
 
 // Long count launches: held to 96 VGPRs (five wavefronts per SIMD by

@@ -29,6 +29,7 @@ struct KParams {
     unsigned long long *counts;
     int32_t *flags;            // [0] overflow, [1] stop, [2] time limit reached
     unsigned long long *t_start; // device wall clock when the first wavefront started (0 = not yet)
+    unsigned long long *wave_done; // PG_RUN_WAVE_TIMES: [0] ~earliest, [1] latest finish (ticks after t_start)
     unsigned long long *emit_ctr;
     int32_t *out;
     unsigned long long *bytes_ctr;

@@ -14,6 +14,8 @@
                                                      # on the R-MAT scale 22 rows by variant and row length
     python -m paper_2004_02369_amd.measure hubs      # the benchmark batch on R-MAT scale 22 with more or fewer
                                                      # rows held as bitmaps (hub bitmap budget sweep)
+    python -m paper_2004_02369_amd.measure tune      # tune the benchmark batch's launch knobs, store the record
+    python -m paper_2004_02369_amd.measure balance   # first / last wavefront finish times (load imbalance)
 """
 from __future__ import annotations
 
@@ -301,6 +303,50 @@ def hubs(args, pg, gg, pt):
         del G
 
 
+def tune_batch(args, pg, gg, pt):
+    """Tune the launch knobs of the serving batch on the serving graph (or
+    the six induced 4-motifs on another workload) and store the record in
+    the package's tuning records (tuned.json) for the benchmark to apply."""
+    from . import serve, tune
+    G = pg.load_graph(*gg.workload(args.workload), device=0)
+    if args.workload == "rmat22_64m":
+        q = {x.name: x for x in serve.catalogue(pg, pt)}
+        plans = [q[n].plans[0] for n in serve.SERVING_BATCH]
+    else:
+        plans = [pg.plan_pattern(s) for s in pt.all_vertex_induced(4)]
+    res = tune.autotune(G, plans, budget_s=args.tune_budget, cache_path=tune.RECORDS, force=True, log=_say)
+    print(json.dumps({"measure": "tune", "workload": args.workload, "knobs": res["knobs"], "ms": res["ms"],
+                      "default_ms": res["default_ms"], "trials": len(res["trials"])}), flush=True)
+
+
+def balance(args, pg, gg, pt):
+    """Load balance of the persistent grid: when the first and the last
+    wavefront ran out of root tasks (device clock, PG_RUN_WAVE_TIMES), for
+    the six induced 4-motifs on Chung-Lu 100K / 1M and the serving batch on
+    R-MAT scale 22, with the knobs the benchmark uses."""
+    from . import serve, tune
+    for wl in ("chunglu_100k_1m", "rmat22_64m"):
+        G = pg.load_graph(*gg.workload(wl), device=0)
+        if wl == "rmat22_64m":
+            q = {x.name: x for x in serve.catalogue(pg, pt)}
+            plans = [q[n].plans[0] for n in serve.SERVING_BATCH]
+        else:
+            plans = [pg.plan_pattern(s) for s in pt.all_vertex_induced(4)]
+        rec = tune.lookup(G, plans, tune.RECORDS)
+        knobs = {k: v for k, v in (rec["knobs"] if rec else {}).items() if v}
+        knobs["flags"] = knobs.get("flags", 0) | pg.PG_RUN_WAVE_TIMES
+        pg.count_ex(G, plans, **knobs)
+        runs = []
+        for _ in range(3):
+            _, st = pg.count_ex(G, plans, **knobs)
+            runs.append({"kernel_ms": st["kernel_ms"], "first_done_ms": st["wave_done_first_ms"],
+                         "last_done_ms": st["wave_done_last_ms"],
+                         "spread_ms": st["wave_done_last_ms"] - st["wave_done_first_ms"]})
+        print(json.dumps({"measure": "balance", "workload": wl, "grid_waves": st["grid_waves"], "knobs": knobs,
+                          "runs": runs}), flush=True)
+        del G
+
+
 def small(args, pg, gg, pt):
     """Launch-bound regime: the six induced 4-motifs on ER 2k/20k, one
     batched launch against six launches, best of several repetitions."""
@@ -324,7 +370,7 @@ def small(args, pg, gg, pt):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion", "c1", "c3", "c5", "rows", "hubs"])
+    ap.add_argument("what", choices=["enum", "motifs5", "small", "inversion", "c1", "c3", "c5", "rows", "hubs", "tune", "balance"])
     ap.add_argument("--pairs", type=int, default=2_000_000)
     ap.add_argument("--seed", type=int, default=5)
     ap.add_argument("--budgets", default="1024,4096,16384,32768")
@@ -351,6 +397,11 @@ def main(argv=None):
     elif args.what == "c3":
         args.workload = args.workload or "rmat20_16m"
         c3(args, pg, gg, pt)
+    elif args.what == "balance":
+        balance(args, pg, gg, pt)
+    elif args.what == "tune":
+        args.workload = args.workload or "rmat22_64m"
+        tune_batch(args, pg, gg, pt)
     elif args.what == "hubs":
         args.workload = args.workload or "rmat22_64m"
         hubs(args, pg, gg, pt)

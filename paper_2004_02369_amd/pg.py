@@ -24,6 +24,7 @@ PG_EINVAL, PG_ENOMEM, PG_EDEVICE, PG_EOVERFLOW, PG_EUNSUPPORTED, PG_ETIMEDOUT = 
 PG_EDGE, PG_ANTI_EDGE = 0, 1
 PG_PLAN_AUTO, PG_PLAN_LINEAR_EXT, PG_PLAN_PARTIAL_ORDER = 0, 1, 2
 PG_RUN_COUNT_BYTES, PG_RUN_NO_MODE_B, PG_RUN_NO_TASK_BATCH, PG_RUN_LIGHT_KERNEL, PG_RUN_NO_SHARE = 1, 2, 4, 8, 16
+PG_RUN_WAVE_TIMES = 32
 PG_JOB_COUNT, PG_JOB_EXISTS = 0, 1
 
 _STATUS = {PG_EINVAL: "EINVAL", PG_ENOMEM: "ENOMEM", PG_EDEVICE: "EDEVICE", PG_EOVERFLOW: "EOVERFLOW",
@@ -82,7 +83,8 @@ class pg_run_config(ctypes.Structure):
 class pg_run_stats(ctypes.Structure):
     _fields_ = [("kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("logical_bytes", ctypes.c_uint64), ("root_tasks", ctypes.c_uint64),
-                ("grid_waves", ctypes.c_int32), ("chunk", ctypes.c_int32), ("tasks_started", ctypes.c_uint64)]
+                ("grid_waves", ctypes.c_int32), ("chunk", ctypes.c_int32), ("tasks_started", ctypes.c_uint64),
+                ("wave_done_first_ms", ctypes.c_double), ("wave_done_last_ms", ctypes.c_double)]
 
 
 MATCH_CB = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_void_p)
@@ -346,7 +348,8 @@ def count_noalloc(graph: Graph, plans, stream=None, **knobs):
 def _stats(st):
     return {"kernel_ms": st.kernel_ms, "total_ms": st.total_ms, "logical_bytes": st.logical_bytes,
             "root_tasks": st.root_tasks, "grid_waves": st.grid_waves, "chunk": st.chunk,
-            "tasks_started": st.tasks_started}
+            "tasks_started": st.tasks_started, "wave_done_first_ms": st.wave_done_first_ms,
+            "wave_done_last_ms": st.wave_done_last_ms}
 
 
 def count(graph: Graph, plans, stream=None, **kw):

@@ -533,6 +533,11 @@ def catalogue_specs(pt):
     return ent
 
 
+# The catalogue's count queries that finish alone on the serving graph (R-MAT
+# 2^22 vertices, 2^26 edges) and fit in 64 bits: the benchmark's batch.
+SERVING_BATCH = ["triangle", "wedge", "induced_wedge", "clique4", "book3", "cricket"]
+
+
 def catalogue(pg, pt):
     """The query catalogue: (name, kind, plans), one plan per typed pattern:
     entries that ask the same question (K4 and the induced K4) share a plan,

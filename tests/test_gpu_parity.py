@@ -221,6 +221,19 @@ def test_merge_model_bytes_deterministic(pg):
     assert len(seen) == 1 and seen.pop() > 0
 
 
+def test_wave_finish_times(pg):
+    """PG_RUN_WAVE_TIMES changes no count and reports 0 <= first <= last
+    finish, within the kernel's duration."""
+    g = gg.chung_lu(3000, 24000, 2.1, 300.0, seed=21)
+    say("wave finish times")
+    Gd = G(pg, g)
+    plans = [pg.plan_pattern(s) for s in pt.all_vertex_induced(4)]
+    want = pg.count(Gd, plans)
+    c, st = pg.count_ex(Gd, plans, flags=pg.PG_RUN_WAVE_TIMES)
+    assert c == want
+    assert 0 <= st["wave_done_first_ms"] <= st["wave_done_last_ms"] <= st["kernel_ms"] * 1.5 + 1.0
+
+
 def test_relabelling_invariance(pg):
     g = gg.chung_lu(2500, 15000, 2.1, 250.0, seed=5)
     specs = pt.all_vertex_induced(4)

@@ -34,8 +34,8 @@ def test_search_cuts_slow_trials_with_a_time_limit():
     calls = []
     cost = lambda k: 1000.0 if k["a"] == 5 else 50.0 + k["a"]
     best, ms, trials = tune.search(_measure_from(cost, calls=calls), SPACE, start={"a": 3, "b": 10, "c": 0})
-    assert calls[0][1] == 0                      # the starting point runs without a limit
-    assert all(lim > 0 for _, lim in calls[1:])  # every trial has one
+    assert calls[0][1] == 0                      # the starting point once without a limit,
+    assert all(lim > 0 for _, lim in calls[1:])  # then like every trial, under one
     slow = [t for k, t in trials if k["a"] == 5]
     assert slow and all(math.isinf(t) for t in slow)
     assert best["a"] == 1 and ms == 51.0
