@@ -664,6 +664,8 @@ def main(argv=None):
     ap.add_argument("--mix-limit-ms", type=int, default=120000, help="time limit of one launch in the mix")
     ap.add_argument("--light-ms", type=float, default=100.0, help="heavy/light cut (ms at a slot's grid)")
     ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--window-ms", type=float, default=0.0,
+                    help="cut heavy launches into root-task windows of about this many ms (0 = whole launches)")
     ap.add_argument("--trace", default="", help="write per-launch and per-request records to TRACE.<qps>.json")
     args = ap.parse_args(argv)
 
@@ -697,7 +699,7 @@ def main(argv=None):
     print(json.dumps({"catalogue": head}), flush=True)
     for lam in [float(x) for x in args.qps.split(",")]:
         srv = Server(G, pool, slots=slots, time_limit_ms=args.mix_limit_ms,
-                     policy=policy_from(keep, alone, slots, light_ms=args.light_ms))
+                     policy=policy_from(keep, alone, slots, light_ms=args.light_ms), window_ms=args.window_ms)
         times, picks = poisson_arrivals(lam, args.queries, len(keep), args.seed)
         say(f"lambda {lam:g}: {args.queries} queries over {times[-1]:.1f} s")
         reqs, t0 = run_open_loop(srv, keep, times, picks,
@@ -705,7 +707,12 @@ def main(argv=None):
         summ = summarize(reqs, t0)
         mism = sum(1 for r in reqs if r.error is None and r.result != alone[r.query.name][0])
         summ.update({"qps_offered": lam, "launches": srv.launches, "merged_requests": srv.merged_requests,
-                     "mismatches_vs_alone": mism})
+                     "mismatches_vs_alone": mism, "window_ms": args.window_ms, "windows_run": srv.windows_run})
+        per = collections.defaultdict(list)
+        for r in reqs:
+            if r.error is None:
+                per[r.query.name].append(1e3 * (r.done - r.arrival))
+        summ["p50_ms_by_query"] = {k: sorted(v)[len(v) // 2] for k, v in sorted(per.items())}
         print(json.dumps(summ), flush=True)
         if args.trace:
             with open(f"{args.trace}.{lam:g}.json", "w") as f:
