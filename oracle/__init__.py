@@ -31,7 +31,13 @@ from functools import lru_cache
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SO = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1 builds and loads liboracle_san.so instead, with
+# AddressSanitizer and UndefinedBehaviorSanitizer (the process must then have
+# libasan preloaded; tests/test_sanitizers.py runs the oracle's tests so).
+_SAN = os.environ.get("ORACLE_SANITIZE", "") == "1"
+_SO = os.path.join(_HERE, "liboracle_san.so" if _SAN else "liboracle.so")
+_FLAGS = (["-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+           "-fno-sanitize-recover=undefined"] if _SAN else ["-O2"])
 
 
 def build(force: bool = False) -> str:
@@ -39,7 +45,7 @@ def build(force: bool = False) -> str:
     src = os.path.join(_HERE, "oracle.c")
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
         tmp = _SO + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-Wall", "-shared", "-fPIC", "-pthread", src, "-o", tmp])
+        subprocess.check_call(["gcc", *_FLAGS, "-Wall", "-shared", "-fPIC", "-pthread", src, "-o", tmp])
         os.replace(tmp, _SO)
     return _SO
 
