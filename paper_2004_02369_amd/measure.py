@@ -304,14 +304,17 @@ def hubs(args, pg, gg, pt):
 
 
 def tune_batch(args, pg, gg, pt):
-    """Tune the launch knobs of the serving batch on the serving graph (or
-    the six induced 4-motifs on another workload) and store the record in
-    the package's tuning records (tuned.json) for the benchmark to apply."""
+    """Tune the launch knobs of the serving batch on the serving graph, of
+    K5 and the induced K5 (the 5-vertex plans that finish) on R-MAT scale
+    20, or of the six induced 4-motifs on another workload, and store the
+    record in the package's tuning records (tuned.json)."""
     from . import serve, tune
     G = pg.load_graph(*gg.workload(args.workload), device=0)
     if args.workload == "rmat22_64m":
         q = {x.name: x for x in serve.catalogue(pg, pt)}
         plans = [q[n].plans[0] for n in serve.SERVING_BATCH]
+    elif args.workload == "rmat20_16m":
+        plans = [pg.plan_pattern(pt.all_vertex_induced(5)[-1]), pg.plan_pattern(pt.clique(5))]
     else:
         plans = [pg.plan_pattern(s) for s in pt.all_vertex_induced(4)]
     res = tune.autotune(G, plans, budget_s=args.tune_budget, cache_path=tune.RECORDS, force=True, log=_say)

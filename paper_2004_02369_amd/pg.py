@@ -315,9 +315,11 @@ def run_config(**kw) -> pg_run_config:
 
 
 def count_ex(graph: Graph, plans, stream=None, **knobs):
-    """Counts and stats of one launch.  knobs: grid_waves, chunk, flags,
-    time_limit_ms, hub_min_degree (pg_run_config).  A run that reaches its
-    time limit raises PGError with status PG_ETIMEDOUT."""
+    """Counts and stats of one launch.  knobs: the fields of pg_run_config
+    (RUN_KNOBS: grid, claim chunk, flags, time limit, bitmap and scan degree
+    thresholds, leaf-batching limit, root-task window).  A run that reaches
+    its time limit raises PGError with status PG_ETIMEDOUT (its partial
+    counts and stats ride on the exception as .counts and .stats)."""
     plans = list(plans)
     arr = (ctypes.c_void_p * len(plans))(*[p._h.value for p in plans])
     out = (ctypes.c_uint64 * len(plans))()
