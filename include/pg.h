@@ -212,10 +212,7 @@ typedef struct {
                               so counts over windows that partition the tasks sum to the full
                               counts; tasks come costliest first.  0, 0 = every task */
     int32_t task_end;      /* 0 = to the last task */
-    int32_t scan_max_degree; /* membership in a row of at most this degree (<= 32) is tested by
-                                scanning it (independent loads) instead of a binary search;
-                                0 = library default, -1 = never */
-    int32_t reserved;      /* must be zero */
+    int32_t reserved[2];   /* must be zero */
 } pg_run_config;
 
 #define PG_RUN_COUNT_BYTES 1  /* also count the merge-model bytes of every set operation */

@@ -160,10 +160,6 @@ inline pg_job::~pg_job() {
 namespace {
 
 constexpr int64_t kHubMinDegree = 16;
-// rows of at most this degree may be scanned for membership; col carries
-// this many padding entries so a scan may read past a row's end
-constexpr int32_t kScanMaxDegree = 32;
-constexpr int32_t kScanDefault = 0;
 constexpr long long kArenaInts = 32768;  // per wavefront
 constexpr int64_t kHubBudgetBytes = int64_t(1) << 30;
 // label-sorted row copy: at most this many label offsets (4 bytes each)
@@ -279,7 +275,7 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
         }
         if (n_labels > 0) {
             const int32_t stride = n_labels + 1;
-            std::vector<int32_t> ext((size_t)(4 * mu) + kScanMaxDegree, INT32_MAX);
+            std::vector<int32_t> ext((size_t)(4 * mu));
             std::copy(col.begin(), col.end(), ext.begin());
             std::vector<int32_t> off((size_t)n * (size_t)stride, 0);
             for (int32_t r = 0; r < n; r++) {
@@ -294,11 +290,8 @@ pg_status pg_load_graph(int32_t n, int64_t m, const int32_t *src, const int32_t 
             if ((st = upload(&g->col, ext, &g->device_bytes))) return st;
             if ((st = upload(&g->lab_off, off, &g->device_bytes))) return st;
             g->n_labels = n_labels;
-        } else {
-            col.resize(col.size() + kScanMaxDegree, INT32_MAX);  // scans may read past a row's end
-            st = upload(&g->col, col, &g->device_bytes);
-            col.resize(col.size() - kScanMaxDegree);
-            if (st) return st;
+        } else if ((st = upload(&g->col, col, &g->device_bytes))) {
+            return st;
         }
         if ((st = upload(&g->up, up, &g->device_bytes))) return st;
         // hub rows also as dense bitmaps: the highest-degree vertices (rank
@@ -471,11 +464,10 @@ pg_status check_args(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, 
             set_error("bad root-task window");
             return PG_EINVAL;
         }
-        if (cfg->scan_max_degree < -1 || cfg->scan_max_degree > kScanMaxDegree) {
-            set_error("scan_max_degree must be in [-1, 32]");
+        if (cfg->reserved[0] || cfg->reserved[1]) {
+            set_error("pg_run_config.reserved must be zero");
             return PG_EINVAL;
         }
-        if (cfg->reserved) { set_error("pg_run_config.reserved must be zero"); return PG_EINVAL; }
     }
     return PG_OK;
 }
@@ -654,7 +646,6 @@ pg::KParams params(const pg_graph *g, const LaunchPlan &L, const void *trie_dev,
     P.mode = la.mode;
     P.run_flags = cfg ? cfg->flags : 0;
     P.batch_max_avg = cfg ? cfg->batch_max_avg : 0;
-    P.scan_max = !cfg || cfg->scan_max_degree == 0 ? kScanDefault : std::max(0, cfg->scan_max_degree);
     P.mark = la.mark_dev;
     P.mark_words = la.mark_words;
 

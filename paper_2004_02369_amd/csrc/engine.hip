@@ -206,32 +206,14 @@ __device__ __forceinline__ void add_runs(T *cnt, int l, bool valid, bool ok, int
     }
 }
 
-// membership of key in a short part of a row (n <= 32) by scanning it: the
-// loads do not depend on each other, so they are in flight together (col
-// carries padding, so reading up to 8 entries past a row's end stays in it)
-__device__ __forceinline__ bool scan_row(const int32_t *__restrict__ p, int32_t n, int32_t key) {
-    bool hit = false;
-#pragma unroll
-    for (int i = 0; i < 32; i += 8) {
-        if (i >= n) break;
-        int32_t v[8];
-#pragma unroll
-        for (int j = 0; j < 8; j++) v[j] = p[i + j];
-#pragma unroll
-        for (int j = 0; j < 8; j++) hit |= (i + j < n) && v[j] == key;
-    }
-    return hit;
-}
-
 // membership of e in the row of r.owner: one load for a hub (dense bitmap),
-// a scan for a short row, a binary search otherwise (the variant per degree
-// bucket: hub_start and scan_max are launch knobs)
+// a binary search otherwise (the variant per degree bucket: hub_start is a
+// launch knob)
 __device__ __forceinline__ bool in_row(const KParams &P, const RowRef &r, int32_t e) {
     if (r.owner >= P.hub_start) {
         const uint32_t w = P.hub_bits[(long long)(r.owner - P.hub_start) * P.hub_words + (e >> 5)];
         return (w >> (e & 31)) & 1u;
     }
-    if (r.n <= P.scan_max && r.owner >= 0) return scan_row(r.p, r.n, e);
     return contains(r.p, r.n, e);
 }
 
@@ -242,7 +224,6 @@ __device__ __forceinline__ bool in_range(const KParams &P, const int32_t *p, int
         const uint32_t w = P.hub_bits[(long long)(owner - P.hub_start) * P.hub_words + (e >> 5)];
         return (w >> (e & 31)) & 1u;
     }
-    if (n <= P.scan_max && owner >= 0) return scan_row(p, n, e);
     return contains(p, n, e);
 }
 

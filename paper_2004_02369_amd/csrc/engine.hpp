@@ -49,7 +49,6 @@ struct KParams {
     int32_t mode;
     int32_t run_flags;
     int32_t batch_max_avg;     // leaf batching only while parents average at most this many candidates; 0 = always
-    int32_t scan_max;          // rows of at most this degree are scanned for membership (col is padded)
     uint32_t *mark;            // domains: per plan, a bitmap of mark_words words over rank ids (nullptr = off)
     long long mark_words;
     long long task_begin;      // root tasks [task_begin, task_end) of this launch; task_end 0 = to the last

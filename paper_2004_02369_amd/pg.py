@@ -77,7 +77,7 @@ class pg_run_config(ctypes.Structure):
     _fields_ = [("grid_waves", ctypes.c_int32), ("chunk", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("time_limit_ms", ctypes.c_int32), ("hub_min_degree", ctypes.c_int32),
                 ("batch_max_avg", ctypes.c_int32), ("task_begin", ctypes.c_int32), ("task_end", ctypes.c_int32),
-                ("scan_max_degree", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class pg_run_stats(ctypes.Structure):
@@ -303,7 +303,7 @@ def plan_pattern(spec, mode: int = PG_PLAN_AUTO, anchor: int | None = None) -> P
 # --------------------------------------------------------------- counting
 
 RUN_KNOBS = ("grid_waves", "chunk", "flags", "time_limit_ms", "hub_min_degree", "batch_max_avg", "task_begin",
-             "task_end", "scan_max_degree")
+             "task_end")
 
 
 def run_config(**kw) -> pg_run_config:
@@ -316,8 +316,8 @@ def run_config(**kw) -> pg_run_config:
 
 def count_ex(graph: Graph, plans, stream=None, **knobs):
     """Counts and stats of one launch.  knobs: the fields of pg_run_config
-    (RUN_KNOBS: grid, claim chunk, flags, time limit, bitmap and scan degree
-    thresholds, leaf-batching limit, root-task window).  A run that reaches
+    (RUN_KNOBS: grid, claim chunk, flags, time limit, bitmap degree
+    threshold, leaf-batching limit, root-task window).  A run that reaches
     its time limit raises PGError with status PG_ETIMEDOUT (its partial
     counts and stats ride on the exception as .counts and .stats)."""
     plans = list(plans)

@@ -2,11 +2,9 @@
 
 The knobs (pg_run_config):
 
-* ``hub_min_degree`` and ``scan_max_degree`` -- the intersection variant
-  per degree bucket: rows of at least hub_min_degree are probed through
-  their dense bitmap (one load), rows of at most scan_max_degree by a scan
-  (independent loads), the rows in between by binary search over the
-  sorted row;
+* ``hub_min_degree`` -- the intersection variant per degree bucket: rows
+  of at least this degree are probed through their dense bitmap (one
+  load), shorter rows by binary search over the sorted row;
 * ``chunk`` -- the largest claim of root tasks; the guided claim grows from 1
   at the costliest tasks to this at the cheapest, so it sets the chunk per
   cost (degree) bucket;
@@ -32,12 +30,11 @@ import time
 
 SPACE = {
     "hub_min_degree": [0, 32, 64, 128, 256, 1024, -1],
-    "scan_max_degree": [0, 4, 8, 16, 32],
     "chunk": [4, 8, 16, 32, 64, 128, 256],
     "batch_max_avg": [0, 8, 16, 32, 64, 128, 512],
     "flags": [0, 4, 8],  # 4 = PG_RUN_NO_TASK_BATCH, 8 = PG_RUN_LIGHT_KERNEL
 }
-DEFAULT = {"hub_min_degree": 0, "scan_max_degree": 0, "chunk": 0, "batch_max_avg": 0, "flags": 0}
+DEFAULT = {"hub_min_degree": 0, "chunk": 0, "batch_max_avg": 0, "flags": 0}
 
 
 class InconsistentCounts(RuntimeError):

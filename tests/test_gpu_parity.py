@@ -200,11 +200,11 @@ def test_batched_equals_single_and_perturbations(pg, orc):
                                (100, 8, pg.PG_RUN_NO_TASK_BATCH | pg.PG_RUN_NO_MODE_B)]:
         say("perturbation", grid, chunk, flags)
         assert pg.count(Gd, plans, grid_waves=grid, chunk=chunk, flags=flags) == batched
-    # intersection variants per degree bucket: scans of short rows, binary
-    # search, bitmaps, in every mix
-    for scan, hub in [(4, 0), (8, 64), (16, -1), (32, 0), (32, -1), (-1, -1)]:
-        say("variants", scan, hub)
-        assert pg.count(Gd, plans, scan_max_degree=scan, hub_min_degree=hub) == batched
+    # intersection variants per degree bucket: bitmaps from several degrees
+    # on, binary search below (or everywhere)
+    for hub in (0, 32, 64, 1000, -1):
+        say("variants", hub)
+        assert pg.count(Gd, plans, hub_min_degree=hub) == batched
 
 
 def test_merge_model_bytes_deterministic(pg):
