@@ -233,7 +233,9 @@ __device__ __forceinline__ bool in_range(const KParams &P, const int32_t *p, int
 __shared__ unsigned long long fac_lds[kP];
 
 // kFac: the trie may hold kFactor nodes
-template <bool kAV, bool kFac>
+// kCnt: the build for long count launches (no existence stop, emission or
+// domain marks), where those paths fold away at compile time
+template <bool kAV, bool kFac, bool kCnt = false>
 struct Ctx {
     const KParams P;  // by value: a reference to the kernel argument would force a private copy
     Lds &L;
@@ -452,14 +454,14 @@ struct Ctx {
     // pidx for the varying level vl0, ptask for parent-slot levels, pmode).
     __device__ __forceinline__ void count_batch(const Node &N, int np) {
         const int x = N.level;
-        const bool emit = N.kind == kEmit;
+        const bool emit = !kCnt && N.kind == kEmit;
         int my_nseg = 0, my_tot = 0;
         const int32_t *sp0 = nullptr, *sp1 = nullptr, *sp2 = nullptr;
         int32_t sl0 = 0, sl1 = 0, sl2 = 0;
         int so0 = -1, so1 = -1, so2 = -1;  // segment owners (row owner, -1 = a set)
         // domains: a prefix whose anchor image is already in the domain
         // adds nothing
-        if (P.mark && N.anchor_level >= 0 && lane < np && L.pmode[lane] >= 0) {
+        if (!kCnt && P.mark && N.anchor_level >= 0 && lane < np && L.pmode[lane] >= 0) {
             const int32_t v = val(N.anchor_level, lane);
             const uint32_t w =
                 __atomic_load_n(P.mark + (long long)N.plan * P.mark_words + (v >> 5), __ATOMIC_RELAXED);
@@ -763,7 +765,7 @@ struct Ctx {
                 if (!factor) {
                     // domains: this prefix has a match, so its anchor's image
                     // is in the anchor's domain
-                    if (P.mark && contrib && N.anchor_level >= 0) {
+                    if (!kCnt && P.mark && contrib && N.anchor_level >= 0) {
                         const int32_t v = val(N.anchor_level, lane);
                         atomicOr(P.mark + (long long)N.plan * P.mark_words + (v >> 5), 1u << (v & 31));
                     }
@@ -788,7 +790,7 @@ struct Ctx {
                     const unsigned long long s = acc + contrib;
                     if (s < acc) atomicOr(P.flags, 1);
                     acc = s;
-                    if (P.mode == kModeExists && s > 0) {
+                    if (!kCnt && P.mode == kModeExists && s > 0) {
                         atomicOr(P.flags + 1, 1);
                         L.stop = 1;
                     }
@@ -862,7 +864,7 @@ struct Ctx {
     // early exit: another wavefront found a match (existence) or the
     // launch's time limit has passed (then every wavefront is told to stop)
     __device__ __forceinline__ bool stopped() {
-        if (P.mode != kModeExists && !P.time_budget) return false;
+        if ((kCnt || P.mode != kModeExists) && !P.time_budget) return false;
         if (lane == 0) {
             if (__atomic_load_n(P.flags + 1, __ATOMIC_RELAXED)) {
                 L.stop = 1;
@@ -994,7 +996,7 @@ struct Ctx {
             const unsigned long long sum = acc + contrib;
             if (sum < acc) atomicOr(P.flags, 1);
             acc = sum;
-            if (P.mode == kModeExists && sum > 0) {
+            if (!kCnt && P.mode == kModeExists && sum > 0) {
                 atomicOr(P.flags + 1, 1);
                 L.stop = 1;
             }
@@ -1036,7 +1038,7 @@ struct Ctx {
         int drv = -1;
         bool ok = lane < np && (okmask >> lane & 1ull);
         // domains: a parent whose anchor image is already in the domain adds nothing
-        if (ok && anc_level >= 0) {
+        if (!kCnt && ok && anc_level >= 0) {
             const int32_t v = val(anc_level, lane);
             const uint32_t w =
                 __atomic_load_n(P.mark + (long long)anc_plan * P.mark_words + (v >> 5), __ATOMIC_RELAXED);
@@ -1367,8 +1369,8 @@ __device__ __noinline__ bool av_check(const KParams &P, const int32_t *vals, con
 
 // every level value comes from Ctx::val, which knows the batch layout
 // (fixed assignment, root batch, set batch or task batch)
-template <bool kAV, bool kFac>
-__device__ bool Ctx<kAV, kFac>::av_pass(const AVCheck &c, int x, int l, int32_t e) const {
+template <bool kAV, bool kFac, bool kCnt>
+__device__ bool Ctx<kAV, kFac, kCnt>::av_pass(const AVCheck &c, int x, int l, int32_t e) const {
     int32_t vals[kMaxLevels];
     for (int y = 0; y < kMaxLevels; y++) vals[y] = y < x ? val(y, l) : (y == x ? e : 0);
     return av_check(P, vals, c);
@@ -1391,8 +1393,8 @@ __device__ __forceinline__ bool root_pre(const KParams &P, const Node &R, int32_
 }
 
 // anti-vertex checks of a root (the task's rows are loaded)
-template <bool kAV, bool kFac>
-__device__ __forceinline__ bool root_ok(Ctx<kAV, kFac> &C, const Node &R, int l) {
+template <bool kAV, bool kFac, bool kCnt>
+__device__ __forceinline__ bool root_ok(Ctx<kAV, kFac, kCnt> &C, const Node &R, int l) {
     if constexpr (kAV)
         for (int i = 0; i < R.av_count; i++) {
             const AVCheck &c = C.P.avs[R.av_begin + i];
@@ -1405,12 +1407,12 @@ __device__ __forceinline__ bool root_ok(Ctx<kAV, kFac> &C, const Node &R, int l)
 
 // kAV: the trie holds anti-vertex checks (the variant without them keeps
 // the out-of-line check and its call frame out of the hot loops)
-template <bool kAV, bool kPre>
+template <bool kAV, bool kPre, bool kCnt = false>
 __device__ __forceinline__ void match_body(const KParams P) {
     __shared__ Lds L;
     const int lane = threadIdx.x;
     int32_t *buf0 = P.scratch ? P.scratch + (long long)blockIdx.x * P.wave_stride : nullptr;
-    Ctx<kAV, kPre> C(P, L, buf0, lane);
+    Ctx<kAV, kPre, kCnt> C(P, L, buf0, lane);
     C.arena = buf0 ? buf0 + P.wave_stride - P.arena_cap : nullptr;
     if (lane < kMaxLevels) {
         // a valid vertex in every slot of the fixed assignment
@@ -1435,7 +1437,8 @@ __device__ __forceinline__ void match_body(const KParams P) {
     wsync();
     // share groups apply to batched count and existence launches (not to
     // emission, domain marks, or level-2 expansion one root task at a time)
-    const bool share_on = !(P.run_flags & (PG_RUN_NO_TASK_BATCH | PG_RUN_NO_SHARE)) && !P.mark && P.mode != kModeEmit;
+    const bool share_on =
+        !(P.run_flags & (PG_RUN_NO_TASK_BATCH | PG_RUN_NO_SHARE)) && (kCnt || (!P.mark && P.mode != kModeEmit));
     // this launch's window of root tasks: [t_lo, t_hi) of the edge tasks
     // followed by the vertex tasks
     const long long t_lo = P.task_begin;
@@ -1508,7 +1511,7 @@ __device__ __forceinline__ void match_body(const KParams P) {
                 C.plev0 = 0;
                 C.plev1 = edge_phase ? 1 : -1;
                 C.vl0 = -1;
-                C.anc_level = P.mark ? uni(R.anchor_level) : -1;
+                C.anc_level = !kCnt && P.mark ? uni(R.anchor_level) : -1;
                 C.anc_plan = uni(R.plan);
                 if constexpr (!kPre) okr = lane < np && root_pre(P, R, task_u, task_v);
                 if constexpr (kAV)
@@ -1587,9 +1590,11 @@ __device__ __forceinline__ void match_body(const KParams P) {
 // Long count launches: held to 96 VGPRs (five wavefronts per SIMD by
 // registers; 8.9 KB of LDS per wave then allows 18 per CU).  The kernel is
 // bound by load latency, so resident waves are what hides it; most of the
-// few spills this costs sit in the task-claim loop.
+// few spills this costs sit in the task-claim loop.  Its launches only
+// count (no existence stop, emission or domain marks), so those paths are
+// compiled out.
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) match_kernel(KParams P) {
-    match_body<false, false>(P);
+    match_body<false, false, true>(P);
 }
 
 // The same program at 128 VGPRs and four wavefronts per SIMD, without
@@ -1715,6 +1720,8 @@ hipError_t launch_hub_bits(const int64_t *rp, const int32_t *col, int32_t first,
 }
 
 hipError_t launch_match(const KParams &P, int grid, int variant, hipStream_t s) {
+    // the long-count build has no existence, emission or domain paths
+    if (variant == kVarPlain && (P.mode != kModeCount || P.mark || P.out)) return hipErrorInvalidValue;
     if (variant == kVarAV) hipLaunchKernelGGL(match_kernel_av, dim3(grid), dim3(64), 0, s, P);
     else if (variant == kVarPre) hipLaunchKernelGGL(match_kernel_pre, dim3(grid), dim3(64), 0, s, P);
     else if (variant == kVarLight) hipLaunchKernelGGL(match_kernel_light, dim3(grid), dim3(64), 0, s, P);

@@ -13,7 +13,8 @@ matching kernel:
 * match_kernel_<workload>_pmc.md -- issue, LDS and texture-unit counters.
 
 The benchmark's launches under profile.sh are one bytes-counting run and two
-timed steps; counters are averaged over the timed ones.
+timed steps; counters are averaged over the timed ones (the last
+TIMED_STEPS dispatches of match_kernel).
 """
 from __future__ import annotations
 
@@ -30,6 +31,7 @@ CLOCK_GHZ = 2.4
 SIMDS = 1024
 CUS = 256
 BENCH = "python3 bench.py --steps 2 --warmup 0 --no-cpu-baseline --no-extras"
+TIMED_STEPS = 2
 
 
 def kernel_hash(root: str) -> str:
@@ -53,8 +55,8 @@ def counters(path: str, kernel: str):
 
 
 def timed(disp):
-    """Counters of the timed dispatches (all but the first, the bytes run)."""
-    vals = list(disp.values())[1:] or list(disp.values())
+    """Counters of the timed dispatches (the last TIMED_STEPS)."""
+    vals = list(disp.values())[-TIMED_STEPS:]
     keys = set().union(*vals)
     return {k: sum(v.get(k, 0.0) for v in vals) / len(vals) for k in keys}
 
@@ -88,7 +90,7 @@ def main(argv=None):
     trace = [r for r in csv.DictReader(open(find(args.raw, "prof_kt", "kernel_trace.csv")))
              if r["Kernel_Name"].startswith(KERNEL)]
     durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6 for r in trace]
-    timed_ms = durs[1:] or durs
+    timed_ms = durs[-TIMED_STEPS:]
     avg_timed = sum(timed_ms) / len(timed_ms)
     lines = [f"# pg::match_kernel on {wl} (the benchmark's batch in one launch): kernel trace", "",
              "Command (run from the repository root):", "",
@@ -99,8 +101,9 @@ def main(argv=None):
     for r in stats:
         lines.append(f"| {r['Name'][:90]} | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
                      f"{float(r['MinNs']) / 1e6:.3f} | {float(r['MaxNs']) / 1e6:.3f} |")
-    lines += ["", f"match_kernel dispatches in order (ms): {', '.join(f'{d:.1f}' for d in durs)}; the first is "
-              f"the bytes-counting run, the others are the timed steps: average {avg_timed:.1f} ms."]
+    lines += ["", f"match_kernel dispatches in order (ms): {', '.join(f'{d:.1f}' for d in durs)}; the last "
+              f"{TIMED_STEPS} are the timed steps (the bytes-counting run, if listed, comes first): "
+              f"average {avg_timed:.1f} ms."]
     if bench:
         lines.append(f"bench.py's HIP-event average in a plain run of the same workload: {bench['kernel_ms']:.1f} ms.")
     with open(os.path.join(args.out, f"match_kernel_{wl}_kernel_trace.md"), "w") as f:
