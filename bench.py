@@ -45,9 +45,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, kernel_hash):
+def measured_traffic(workload, kernel_hash, knobs):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
+    it was taken on the current kernel source with the same launch knobs;
+    else None."""
     path = os.path.join(ROOT, "profiles", f"match_kernel_{workload}_traffic.txt")
     t = {}
     try:
@@ -58,7 +59,7 @@ def measured_traffic(workload, kernel_hash):
                     t[k.strip()] = v.strip()
     except OSError:
         return None
-    if t.get("kernel_hash") != kernel_hash:
+    if t.get("kernel_hash") != kernel_hash or t.get("knobs") != json.dumps(knobs, sort_keys=True):
         return None
     try:
         return float(t["hbm_bytes_per_launch"])
@@ -286,7 +287,7 @@ def main():
     }
 
     khash = kernel_source_hash()
-    traffic = measured_traffic(WORKLOAD, khash)
+    traffic = measured_traffic(WORKLOAD, khash, knobs)
     achieved = logical_bytes / (avg_kernel_ms * 1e-3) / 1e9
     achievable = achievable_bandwidth()
     say(f"streaming read {achievable:.0f} GB/s")

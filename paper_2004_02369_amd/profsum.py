@@ -139,7 +139,10 @@ def main(argv=None):
         t += ["", f"Algorithmic (merge-model) bytes per launch: {bench['roofline']['algorithmic_bytes_per_launch']:.4e}",
               f"Streaming-read bandwidth measured in the same bench run: "
               f"{bench['roofline']['achievable_read_gbs']:.0f} GB/s"]
-    t += ["", f"kernel_hash: {khash}", f"hbm_bytes_per_launch: {hbm:.6e}"]
+    t += ["", f"kernel_hash: {khash}"]
+    if bench:
+        t.append(f"knobs: {json.dumps(bench.get('knobs', {}), sort_keys=True)}")
+    t.append(f"hbm_bytes_per_launch: {hbm:.6e}")
     with open(os.path.join(args.out, f"match_kernel_{wl}_traffic.txt"), "w") as f:
         f.write("\n".join(t) + "\n")
 

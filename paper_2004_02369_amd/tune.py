@@ -30,8 +30,8 @@ import time
 
 SPACE = {
     "hub_min_degree": [0, 32, 64, 128, 256, 1024, -1],
-    "chunk": [4, 8, 16, 32, 64, 128, 256],
-    "batch_max_avg": [0, 8, 16, 32, 64, 128, 512],
+    "chunk": [4, 8, 16, 32, 64, 128, 256, 512, 1024],
+    "batch_max_avg": [0, 8, 16, 32, 64, 128, 512, 2048],
     "flags": [0, 4, 8],  # 4 = PG_RUN_NO_TASK_BATCH, 8 = PG_RUN_LIGHT_KERNEL
 }
 DEFAULT = {"hub_min_degree": 0, "chunk": 0, "batch_max_avg": 0, "flags": 0}
