@@ -1612,7 +1612,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ma
     match_body<false, true>(P);
 }
 
-__global__ void __launch_bounds__(64) match_kernel_av(KParams P) { match_body<true, true>(P); }
+// anti-vertex checks: held to 128 VGPRs (four waves per SIMD) like the
+// light build.  Left free it takes about 190 and two waves per SIMD; the
+// spills of the out-of-line check's image table cost less than the halved
+// residency (p7 on a 1M-edge Chung-Lu graph 32.7 -> 27.0 ms)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) match_kernel_av(KParams P) {
+    match_body<true, true>(P);
+}
 
 static const void *variant_fn(int variant) {
     switch (variant) {
