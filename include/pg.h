@@ -194,7 +194,8 @@ typedef struct {
     int32_t grid_waves;    /* persistent wavefronts; 0 = auto: the resident wavefronts of the
                               kernel build the launch runs on, fewer for small launches (about
                               64 root tasks per program leaf per wave, at least one per CU) */
-    int32_t chunk;         /* root tasks claimed per atomic; 0 = auto */
+    int32_t chunk;         /* largest claim of root tasks (claims grow from 1 over the costliest
+                              tasks); 0 = auto (64) */
     int32_t flags;         /* PG_RUN_* */
     int32_t time_limit_ms; /* stop every wavefront once this long has passed on the device clock
                               since the launch's first wavefront started, and return
@@ -249,7 +250,10 @@ pg_status pg_count(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, ui
                    void *hip_stream);
 
 /* pg_count with launch knobs (NULL = defaults) and run statistics
- * (NULL = not wanted).  Results do not depend on the knobs. */
+ * (NULL = not wanted).  Results do not depend on the knobs.  Plans whose
+ * programs are identical (different patterns can compile to the same
+ * plan, as K5 and the induced K5 do) are counted once per launch and their
+ * counts copied; the statistics describe that launch. */
 pg_status pg_count_ex(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_t *counts,
                       const pg_run_config *cfg, pg_run_stats *stats, void *hip_stream);
 

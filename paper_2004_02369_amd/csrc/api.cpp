@@ -795,6 +795,50 @@ pg_status run(pg_graph *g, const pg_plan *const *plans, int32_t n_plans, uint64_
     return read_ctl(ctl, n_plans, counts, emitted);
 }
 
+// Everything the counting kernel reads of a plan, written out: two plans
+// with equal keys count the same subgraphs on every graph.
+std::vector<int64_t> count_key(const pg::PlanImpl &P) {
+    std::vector<int64_t> v{P.k, P.anchor, (int64_t)P.count_progs.size()};
+    auto put = [&](const pg::Level &L) {
+        for (uint32_t x : {L.isect, L.diff, L.lo, L.hi, L.excl, L.excl_in, L.t_isect, L.t_diff}) v.push_back(x);
+        for (int32_t x : {L.base, L.label, L.group, L.pv, (int32_t)L.avs.size()}) v.push_back(x);
+        for (const pg::AVCheck &c : L.avs) {
+            v.push_back(c.nbr);
+            v.push_back(c.label);
+            for (int i = 0; i < pg::kMaxLevels; i++) v.push_back(c.xmask[i]);
+        }
+    };
+    for (const pg::Program &pr : P.count_progs) {
+        v.push_back((int64_t)pr.lev.size());
+        v.push_back((int64_t)pr.factors.size());
+        v.push_back((int64_t)(pr.mult >> 1));  // split: mult may exceed INT64_MAX
+        v.push_back((int64_t)(pr.mult & 1u));
+        for (const pg::Level &L : pr.lev) put(L);
+        for (const pg::Level &L : pr.factors) put(L);
+    }
+    return v;
+}
+
+// The distinct plans of a call, and where each plan's count comes from.
+// Different patterns can compile to the same programs (K5 and the induced
+// K5: a clique has no non-adjacent pair to add an anti-edge to); such plans
+// are counted once per launch.
+void distinct_plans(const pg_plan *const *plans, int32_t n, std::vector<const pg_plan *> *uniq,
+                    std::vector<int32_t> *from) {
+    std::vector<std::vector<int64_t>> keys;
+    from->assign((size_t)n, 0);
+    for (int32_t i = 0; i < n; i++) {
+        std::vector<int64_t> k = count_key(plans[i]->impl);
+        size_t j = 0;
+        while (j < keys.size() && keys[j] != k) j++;
+        if (j == keys.size()) {
+            keys.push_back(std::move(k));
+            uniq->push_back(plans[i]);
+        }
+        (*from)[(size_t)i] = (int32_t)j;
+    }
+}
+
 constexpr size_t kWsAlign = 256;
 inline size_t align_up(size_t x) { return (x + kWsAlign - 1) & ~(kWsAlign - 1); }
 
@@ -812,7 +856,18 @@ pg_status pg_count_ex(pg_graph *g, const pg_plan *const *plans, int32_t n_plans,
                       const pg_run_config *cfg, pg_run_stats *stats, void *hip_stream) {
     if (!counts) { set_error("counts is NULL"); return PG_EINVAL; }
     try {
-        return run(g, plans, n_plans, counts, cfg, stats, hip_stream, LaunchArgs{}, nullptr);
+        pg_status st = check_args(g, plans, n_plans, cfg);
+        if (st) return st;
+        std::vector<const pg_plan *> uniq;
+        std::vector<int32_t> from;
+        distinct_plans(plans, n_plans, &uniq, &from);
+        if ((int32_t)uniq.size() == n_plans)
+            return run(g, plans, n_plans, counts, cfg, stats, hip_stream, LaunchArgs{}, nullptr);
+        std::vector<uint64_t> c(uniq.size(), 0);
+        st = run(g, uniq.data(), (int32_t)uniq.size(), c.data(), cfg, stats, hip_stream, LaunchArgs{}, nullptr);
+        if (st == PG_OK || st == PG_ETIMEDOUT || st == PG_EOVERFLOW)
+            for (int32_t i = 0; i < n_plans; i++) counts[i] = c[(size_t)from[(size_t)i]];
+        return st;
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed");
         return PG_ENOMEM;

@@ -60,16 +60,18 @@ def motifs5(args, pg, gg, pt):
     G = pg.load_graph(*gg.workload(args.workload), device=0)
     specs = pt.all_vertex_induced(5) + [pt.clique(5)]
     plans = [pg.plan_pattern(s) for s in specs]
+    knobs = {"chunk": args.chunk} if args.chunk else {}
     t0 = time.perf_counter()
-    counts, st = pg.count_ex(G, plans, time_limit_ms=args.limit_ms)
+    counts, st = pg.count_ex(G, plans, time_limit_ms=args.limit_ms, **knobs)
     batched = time.perf_counter() - t0
     _say(f"batched {batched:.2f} s")
     single = []
     for p in plans:
         t0 = time.perf_counter()
-        pg.count_ex(G, [p], time_limit_ms=args.limit_ms)
+        pg.count_ex(G, [p], time_limit_ms=args.limit_ms, **knobs)
         single.append(time.perf_counter() - t0)
     print(json.dumps({"measure": "motifs5", "workload": args.workload, "n": G.n, "m": G.m, "d_max": G.d_max,
+                      "knobs": knobs,
                       "batched_s": batched, "kernel_ms": st["kernel_ms"], "single_s": single,
                       "single_sum_s": sum(single), "speedup": sum(single) / batched,
                       "k5_equals_induced_k5": counts[-1] == counts[-2], "counts": counts}), flush=True)
@@ -381,6 +383,7 @@ def main(argv=None):
     ap.add_argument("--workload", default=None)
     ap.add_argument("--limit-ms", type=int, default=600000)
     ap.add_argument("--tune-budget", type=float, default=60.0)
+    ap.add_argument("--chunk", type=int, default=0, help="motifs5: largest claim of root tasks (0 = library default)")
     args = ap.parse_args(argv)
     import torch
     from . import graphgen as gg

@@ -207,6 +207,26 @@ def test_batched_equals_single_and_perturbations(pg, orc):
         assert pg.count(Gd, plans, hub_min_degree=hub) == batched
 
 
+def test_identical_plans_counted_once(pg, orc):
+    """K5 and the induced K5 compile to the same programs: a call holding
+    both (and K5 twice, among other plans) runs them once and reports each
+    its count, equal to the oracle's and to single launches."""
+    g = gg.chung_lu(3000, 24000, 2.1, 300.0, seed=21)
+    say("identical plans in one launch")
+    Gd = G(pg, g)
+    specs = [pt.clique(5), pt.clique(3), pt.all_vertex_induced(5)[-1], pt.clique(5), pt.star(3)]
+    plans = [pg.plan_pattern(s) for s in specs]
+    og = orc.Graph.from_tuple(g)
+    want = [orc.count(og, s) for s in specs]
+    assert want[0] == want[2] == want[3] > 0
+    assert pg.count(Gd, plans) == want
+    assert [pg.count(Gd, [p])[0] for p in plans] == want
+    # the launch holds three distinct plans: its merge-model bytes are those of the three alone
+    _, st_all = pg.count_ex(Gd, plans, flags=pg.PG_RUN_COUNT_BYTES)
+    _, st_uniq = pg.count_ex(Gd, [plans[0], plans[1], plans[4]], flags=pg.PG_RUN_COUNT_BYTES)
+    assert st_all["logical_bytes"] == st_uniq["logical_bytes"]
+
+
 def test_merge_model_bytes_deterministic(pg):
     """Claims cover fixed task ranges, so the merge-model byte count of a
     launch is the same for every run and every grid size."""
