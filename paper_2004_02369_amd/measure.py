@@ -131,13 +131,14 @@ def c3(args, pg, gg, pt):
     specs = pt.all_vertex_induced(5) + [pt.clique(5)]
     plans = [pg.plan_pattern(s) for s in specs]
     lo_plan, hi_plan = (int(x) for x in args.plans.split("-"))
+    knobs = {"chunk": args.chunk} if args.chunk else {}
     singles = []
     for i, p in enumerate(plans):
         rec = {"plan": i, "edges": specs[i]["edges"], "core": p.info()["core"], "ms": None, "count": None}
         if not (lo_plan <= i <= hi_plan):
             continue
         try:
-            c, st = pg.count_ex(G, [p], time_limit_ms=args.limit_ms)
+            c, st = pg.count_ex(G, [p], time_limit_ms=args.limit_ms, **knobs)
             rec.update(ms=st["kernel_ms"], count=c[0], root_tasks=st["root_tasks"])
         except pg.PGError as e:
             if e.status != pg.PG_ETIMEDOUT:
@@ -158,9 +159,9 @@ def c3(args, pg, gg, pt):
     done = [r for r in singles if r["ms"] is not None]
     batch = [plans[r["plan"]] for r in done]
     out = {"measure": "c3", "workload": args.workload, "n": G.n, "m": G.m, "d_max": G.d_max,
-           "limit_ms": args.limit_ms, "singles": singles, "finished": len(done)}
+           "limit_ms": args.limit_ms, "knobs": knobs, "singles": singles, "finished": len(done)}
     if done:
-        c, st = pg.count_ex(G, batch)
+        c, st = pg.count_ex(G, batch, **knobs)
         assert c == [r["count"] for r in done], "batched counts differ from the single launches"
         out["batched_ms"] = st["kernel_ms"]
         out["singles_sum_ms"] = sum(r["ms"] for r in done)
@@ -383,7 +384,7 @@ def main(argv=None):
     ap.add_argument("--workload", default=None)
     ap.add_argument("--limit-ms", type=int, default=600000)
     ap.add_argument("--tune-budget", type=float, default=60.0)
-    ap.add_argument("--chunk", type=int, default=0, help="motifs5: largest claim of root tasks (0 = library default)")
+    ap.add_argument("--chunk", type=int, default=0, help="motifs5, c3: largest claim of root tasks (0 = library default)")
     args = ap.parse_args(argv)
     import torch
     from . import graphgen as gg
