@@ -352,3 +352,16 @@ def test_anchored_stabiliser_order():
     assert pg.plan_pattern(pt.chain(4), anchor=0).info()["aut"] == 1
     with pytest.raises(pg.PGError):
         pg.plan_pattern(pt.clique(3), anchor=3)
+
+
+def test_clique_and_induced_clique_compile_to_identical_programs():
+    """A clique has no non-adjacent pair, so its vertex-induced form adds no
+    anti-edge and compiles to the same programs (pg_count_ex then counts the
+    two once per launch); a pattern with a non-adjacent pair does not."""
+    for k in (3, 4, 5):
+        a = pg.plan_pattern(pt.clique(k))
+        b = pg.plan_pattern(pt.clique(k, induced=True))
+        assert a.programs() == b.programs()
+    s = pg.plan_pattern(pt.star(4))
+    si = pg.plan_pattern(pt.star(4, induced=True))
+    assert s.programs() != si.programs()
